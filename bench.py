@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Batched programmable-bootstrapping benchmark on one MI355X.
+
+Workload (default): 4096 independent LWE ciphertexts (n = 630, Torus32,
+sigma 2^-15) of messages uniform in Z_32, bootstrapped with the LIF
+threshold (FHE-Fire) test polynomial at N = 1024, k = 1, l = 3, Bg = 2^7,
+then key-switched (base 2^2, t = 8).  One step = one pass of the hot path
+over the batch: modulus switch, accumulator initialisation, blind rotation
+and sample extraction (one launch), key switch (one launch).  Inputs are
+resident in HBM before the timed region.  `--shape b` runs the second
+shape (N = 2048, l = 2, Bg = 2^10, p = 64).
+
+Prints one JSON line: PBS/s, the roofline of the blind-rotation kernel
+(timed with HIP events on the launch stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one bootstrapping, counted on the textbook radix-2
+# negacyclic transform: per CMux step (k+1) l forward and k+1 inverse
+# N-point transforms of N/2 log2 N butterflies (1 modular product + 1 sum +
+# 1 difference each) and (k+1)^2 l N pointwise products (1 modular product
+# + 1 accumulate each); n CMux steps per bootstrapping.  One modular
+# product is 5 binary64 VALU instructions (mul, fma, mul, rndne, fma), so a
+# butterfly is 7 and a pointwise multiply-accumulate 6 instructions.
+MODMUL_OPS, BFLY_OPS, MAC_OPS = 5, 7, 6
+
+
+def alg_ops_per_pbs(n, N, l):
+    logn = N.bit_length() - 1
+    bfly = (2 * l + 2) * (N // 2) * logn
+    macs = 4 * l * N
+    return n * (bfly * BFLY_OPS + macs * MAC_OPS), n * (bfly + macs)
+
+
+# binary64 VALU issue rate of the chip: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--shape", choices=["a", "b"], default="a")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="bootstrappings the CPU oracle times (0: 2 per host thread)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the bootstrappings of a batch "
+              "are independent; sharding across GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2309_09025_amd import fhesnn as F
+
+    shape = 0 if args.shape == "a" else 1
+    P = F.params_default(shape)
+    B = args.batch
+    sk, evk = F.keygen(P, synth.SEED_KEYS)
+    ctx = F.Context(0)
+    dk = F.evk_upload(ctx, evk)
+    m = synth.messages(synth.SEED_DATA, B, P.p)
+    ct = F.encrypt(sk, m, synth.SEED_ENC)
+    fire, _ = F.lif_luts(4, 2, P.p)
+
+    d_in = F.to_device(ct)
+    d_ext = F.empty_ct(B, P.N + 1)
+    d_out = F.empty_ct(B, P.n + 1)
+    ctx.reserve(P.N, B)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        F.pbs(ctx, dk, fire, d_in, d_ext, keyswitch=False, stream=stream)  # BR + extract
+        if ev:
+            ev[1].record(stream)
+        F.keyswitch(ctx, dk, d_ext, d_out, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    br_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    ks_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    pbs_per_s = B / (ms_per_step / 1e3)
+
+    out = F.to_host(d_out)
+    dec = F.decrypt(sk, out)
+    want = np.where(((m.astype(np.int64) - 4) % P.p) < P.p // 2, 1, -1)
+    decrypt_ok = float((dec == want).mean())
+
+    ops, modmuls = alg_ops_per_pbs(P.n, P.N, P.l)
+    br_avg = sum(br_ms) / len(br_ms)
+    achieved = ops * B / (br_avg / 1e3) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": "blind_rotate_kernel",
+        "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
+        "unit": "TOP/s (binary64 VALU lane-instructions)",
+        "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
+        "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
+        "kernel_ms": round(br_avg, 4),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        OP = O.SHAPE_A if shape == 0 else O.SHAPE_B
+        nt = O.threads()
+        S = min(B, args.cpu_sample or 2 * nt)
+        K = O.keygen(OP, synth.SEED_KEYS, with_ksk=True)
+        octs = O.encrypt(OP, K.s, m[:S], synth.SEED_ENC)
+        v = O.test_poly(OP.N, OP.p, fire)
+        tc = time.perf_counter()
+        ores = O.pbs(K, v, octs, keyswitch=True, nthreads=nt)
+        cdt = time.perf_counter() - tc
+        cpu = {"value": round(S / cdt, 3), "unit": "bootstrappings/sec", "cores": nt,
+               "kind": "oracle",
+               "sample": f"{S} of the {B} bootstrappings (same inputs, keys and test polynomial), "
+                         f"{cdt:.1f} s on {nt} threads",
+               "parity_on_sample": bool(np.array_equal(ores, out[:S]))}
+
+    res = {
+        "metric": "bootstrappings/sec (n=630,N=1024) + encrypted predictions/sec; p99 latency",
+        "value": round(pbs_per_s, 2), "unit": "bootstrappings/sec",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 torus / f64-exact NTT mod P", "data": "synthetic",
+        "config": {"workload": f"batched PBS microbench: {B} fresh LWE(n={P.n}) ciphertexts, "
+                               f"messages uniform in Z_{P.p}, LIF threshold test polynomial, "
+                               f"N={P.N} k=1 l={P.l} Bg=2^{P.bg_bit}, KS base 2^{P.ks_base_bit} t={P.ks_t}",
+                   "batch": B, "n": P.n, "N": P.N, "l": P.l, "bg_bit": P.bg_bit, "p": P.p},
+        "breakdown_ms": {"blind_rotate+extract": round(br_avg, 4),
+                         "keyswitch": round(sum(ks_ms) / len(ks_ms), 4)},
+        "decrypt_ok_fraction": decrypt_ok,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

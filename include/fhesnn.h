@@ -1,0 +1,220 @@
+/*
+ * fhesnn.h -- C ABI of the MI355X encrypted-LIF engine (TFHE programmable
+ * bootstrapping of LWE ciphertexts, plus the integer WeightSum layers that
+ * feed it), after "Efficient Privacy-Preserving Convolutional Spiking Neural
+ * Networks with FHE" (FHE-DiCSNN).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Torus32: q = 2^32; every ciphertext word is a uint32_t and all
+ *    arithmetic on it wraps mod 2^32 (Sec. 2.1, LWE item, with q = 2^32).
+ *  - An LWE ciphertext of dimension d is d+1 words (a_0 .. a_{d-1}, b), b
+ *    last.  Batches are row-major [count][d+1].  Under the LWE key s the
+ *    width is n+1; an extracted, not yet key-switched ciphertext (key z) is
+ *    N+1 words.
+ *  - Messages are int32 residues of Z_p; decryption returns the centred
+ *    representative in {-p/2+1, ..., p/2} (Sec. 2.1, definition of Z_p).
+ *    Encoding is Delta*(m mod p), Delta = 2^32/p.
+ *  - Pointers marked "dev" are device (HBM) pointers owned by the caller;
+ *    "host" pointers are host memory owned by the caller.  The library
+ *    never frees or retains caller pointers beyond the call; device work is
+ *    enqueued on the given stream (a hipStream_t passed as void*; NULL = the
+ *    default stream) and the caller keeps buffers alive until it has
+ *    synchronised that stream.
+ *  - Every function returns FS_OK (0) or a negative FS_E* code; the reason
+ *    is then available from fs_last_error() (thread-local).  Nothing aborts
+ *    and no C++ exception crosses this boundary.
+ *  - Handles (fs_secret, fs_evk, fs_ctx, fs_devkey) are created by the
+ *    library and released by the matching fs_*_free / fs_ctx_destroy.
+ *  - Only k = 1 (one mask polynomial per RLWE sample) is supported.
+ */
+#ifndef FHESNN_H
+#define FHESNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define FS_API __attribute__((visibility("default")))
+#else
+#define FS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FS_OK 0
+#define FS_EINVAL (-1)   /* bad argument: null, shape, non-negacyclic LUT, p not a power of 2 */
+#define FS_ENOMEM (-2)   /* host or device allocation failed                                  */
+#define FS_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed                        */
+#define FS_EPARAM (-4)   /* key / parameter set mismatch                                      */
+#define FS_EBUDGET (-5)  /* request does not fit the memory budget                            */
+#define FS_ENOTSUP (-6)  /* parameter set outside what the kernels implement                  */
+
+#define FS_PARAMS_VERSION 1u
+
+/* TFHE parameter set.
+ *   n           LWE dimension (key s).
+ *   N, k        RLWE ring degree (power of two) and mask size; k must be 1.
+ *   l, bg_bit   gadget levels and log2 of the gadget base Bg (TGSW rows).
+ *   ks_t, ks_base_bit   key-switch digits and log2 of their base.
+ *   p           message modulus, a power of two with p <= 2N.
+ *   sigma_*     Gaussian noise standard deviations on the unit torus.
+ * Kernels exist for (N, l, bg_bit) = (1024, 3, 7) and (2048, 2, 10). */
+typedef struct fs_params {
+  uint32_t n, N, k, l, bg_bit, ks_t, ks_base_bit, p;
+  double sigma_lwe, sigma_bsk, sigma_ksk;
+  uint32_t version; /* FS_PARAMS_VERSION */
+} fs_params;
+
+/* LIF neuron: integer threshold V_th (0 < v_th <= p/2) and leak time
+ * constant tau (tau >= 2; 0 means the IF neuron, tau = infinity), as in
+ * Theorem 3.1 (Eq. DiscretEquation). */
+typedef struct fs_lif {
+  int32_t v_th;
+  uint32_t tau;
+} fs_lif;
+
+typedef struct fs_secret fs_secret; /* client: binary s (n) and z (N)                          */
+typedef struct fs_evk fs_evk;       /* client-built evaluation key: BSK + KSK, host memory     */
+typedef struct fs_ctx fs_ctx;       /* server: device binding, LUT cache, scratch              */
+typedef struct fs_devkey fs_devkey; /* server: HBM-resident BSK (NTT domain) + KSK             */
+
+/* Thread-local text of the last error (never NULL). */
+FS_API const char* fs_last_error(void);
+
+/* Fill *out with a built-in parameter set: shape 0 = n 630, N 1024, l 3,
+ * Bg 2^7, KS base 2^2 t 8, p 32, sigma_lwe = sigma_ksk = 2^-15,
+ * sigma_bsk = 2^-25; shape 1 = the same with N 2048, l 2, Bg 2^10, p 64,
+ * sigma_bsk = 2^-31. */
+FS_API int fs_params_default(int shape, fs_params* out);
+
+/* ---------------------------------------------------------------- client */
+
+/* Key generation (Sec. 2.1: LWE key s, RLWE key z, bootstrapping key
+ * ek = (RGSW(X^{s_1}) .. RGSW(X^{s_n})) realised as BSK_i = TGSW_z(s_i),
+ * and the key-switching key z -> s).  All randomness is drawn from a
+ * ChaCha20 counter stream keyed by `seed` (RFC 8439 block function), so the
+ * keys are a deterministic function of (params, seed).  Host memory only. */
+FS_API int fs_keygen(const fs_params* params, uint64_t seed, fs_secret** sk, fs_evk** evk);
+
+/* LWE encryption of count messages (Sec. 2.1, LWE item):
+ * ct_k = (a, <a,s> + e + Delta*(m_k mod p)).  Ciphertext k draws its mask
+ * and noise from stream object first_index + k of `seed`.
+ * ct_out: host [count][n+1]. */
+FS_API int fs_encrypt(const fs_secret* sk, const int32_t* m, size_t count, uint64_t seed,
+               uint64_t first_index, uint32_t* ct_out);
+
+/* Decryption (Sec. 2.1): m = round((b - <a,key>) p / 2^32) mod p, centred.
+ * dim = n+1 decrypts under s; dim = N+1 under z (extracted samples).
+ * ct: host [count][dim]; m_out: host [count]. */
+FS_API int fs_decrypt(const fs_secret* sk, const uint32_t* ct, size_t count, uint32_t dim,
+               int32_t* m_out);
+
+/* Copies of the key material for inspection (tests):
+ * s: host [n], z: host [N]; bsk: host [n][2l][2][N] (coefficient domain);
+ * ksk: host [N][t][base-1][n+1].  Any output pointer may be NULL. */
+FS_API int fs_secret_export(const fs_secret* sk, int32_t* s, int32_t* z);
+FS_API int fs_evk_export(const fs_evk* evk, uint32_t* bsk, uint32_t* ksk);
+FS_API int fs_evk_params(const fs_evk* evk, fs_params* out);
+
+FS_API void fs_secret_free(fs_secret* sk);
+FS_API void fs_evk_free(fs_evk* evk);
+
+/* Program function -> test polynomial (the Initialization step after
+ * Theorem 2.1): v_i = Delta * f(floor((i p + N) / (2N)) mod p), i < N.
+ * f: host [p] residues.  Returns FS_EINVAL unless f(r + p/2) = -f(r) mod p
+ * for all r (the condition of Theorem 2.1).  v_out: host [N]. */
+FS_API int fs_test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v_out);
+
+/* FHE-Fire and FHE-Reset program functions (Sec. 4.2) as residue tables:
+ * fire[r] = +1 if (r - V_th) mod p < p/2 else -1;
+ * reset[r] = leak(r) on [0, V_th), 0 on [V_th, p/2), -leak(r - p/2) on
+ * [p/2, p/2 + V_th), 0 on [p/2 + V_th, p), with leak(h) = (tau-1)/tau * h
+ * rounded half up (leak = identity for IF).  Either output may be NULL. */
+FS_API int fs_lif_luts(const fs_lif* lif, uint32_t p, int32_t* fire, int32_t* reset);
+
+/* Range condition of Theorem 4.1: M = V_th + max |I|, with
+ * max |I| = max_o sum_i |W[o][i]| * max(|x_lo|, |x_hi|) over inputs in
+ * [x_lo, x_hi].  Writes M to *m_out; returns FS_OK when M <= p/2 and 1 when
+ * the condition is violated (the layer then wraps mod p).  W: host [O][I]. */
+FS_API int fs_lif_range_check(const fs_lif* lif, uint32_t p, const int32_t* W, size_t O, size_t I,
+                       int32_t x_lo, int32_t x_hi, int64_t* m_out);
+
+/* ---------------------------------------------------------------- server */
+
+/* Bind to HIP device `device`. */
+FS_API int fs_ctx_create(int device, fs_ctx** ctx);
+FS_API int fs_ctx_destroy(fs_ctx* ctx);
+
+/* Pre-size the context's scratch for up to max_jobs bootstrappings per
+ * call at ring degree N, so later calls allocate nothing (needed before
+ * stream capture into a graph). */
+FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
+
+/* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
+ * the exact negacyclic transform on the device; the KSK is copied as is.
+ * Synchronous.  The device key is immutable afterwards and may be shared
+ * by calls on any stream of the context's device. */
+FS_API int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk);
+FS_API int fs_devkey_params(const fs_devkey* dk, fs_params* out);
+FS_API size_t fs_devkey_bytes(const fs_devkey* dk);
+FS_API void fs_devkey_free(fs_devkey* dk);
+
+/* WeightSum on ciphertexts (Sec. 4.1, Eq. "noise grows"):
+ * y[o] = add[o] + sum_i W[o][i] * x[i], word by word mod 2^32.
+ * W: dev int32 [O][I]; x: dev [I][dim]; add: dev [O][dim] or NULL;
+ * y: dev [O][dim]; y == add is allowed (in-place accumulate), y must not
+ * overlap x.  dim = ciphertext width (n+1). */
+FS_API int fs_lwe_linear(fs_ctx* ctx, const int32_t* W, size_t O, size_t I, uint32_t dim,
+                  const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream);
+
+/* WeightSum of a 2-D convolution over ciphertext feature maps (Sec. 4.1):
+ * x: dev [Ci][H][Wd][dim]; W: dev int32 [Co][Ci][K][K];
+ * y: dev [Co][Ho][Wo][dim], Ho = (H + 2 pad - K)/stride + 1 (same for Wo);
+ * taps falling in the zero padding contribute nothing.  add as above. */
+FS_API int fs_lwe_conv2d(fs_ctx* ctx, const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd,
+                  uint32_t Co, uint32_t K, uint32_t stride, uint32_t pad, uint32_t dim,
+                  const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream);
+
+/* Word-wise ciphertext sum y = a + b mod 2^32 (homomorphic addition).
+ * a, b, y: dev [words]; y may alias a or b. */
+FS_API int fs_lwe_add(fs_ctx* ctx, const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
+               void* stream);
+
+/* Programmable bootstrapping (Sec. 2.1: KeySwitch o Extract o BlindRotate
+ * o Initialize) of B ciphertexts with one program function.
+ * lut: host [p] residues, negacyclic (else FS_EINVAL).
+ * in: dev [B][n+1]; out: dev [B][n+1] when keyswitch != 0, else the
+ * extracted LWE_z samples, dev [B][N+1]. */
+FS_API int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const uint32_t* in, size_t B,
+           uint32_t* out, int keyswitch, void* stream);
+
+/* One LIF activation of B neurons (Sec. 4.2, Eq. FHE-Fire and
+ * Eq. FHE-Reset): both outputs bootstrap the same input LWE(H):
+ * spike2_out = bootstrap_Fire(LWE(H)) + 1 = LWE(2S), 2S in {0, 2};
+ * v_out = bootstrap_Reset(LWE(H)) = LWE(V').  The threshold is folded into
+ * the Fire function.  h, spike2_out, v_out: dev [B][n+1]; v_out may alias h. */
+FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
+               uint32_t* spike2_out, uint32_t* v_out, void* stream);
+
+/* Key switching z -> s alone (Sec. 2.1, Key Switching step).
+ * in: dev [B][N+1] under z; out: dev [B][n+1] under s. */
+FS_API int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,
+                 void* stream);
+
+/* Negacyclic product through the device's exact NTT (the transform used by
+ * blind rotation; exposed to check it against schoolbook products):
+ * out = sum_{r<R} d_r(X) b_r(X) in Z_{2^32}[X]/(X^N+1).
+ * d: dev int32 [R][N] with |d| <= dmax; b: dev uint32 [R][N]; out: dev [N].
+ * N in {1024, 2048}; FS_EINVAL unless R*N*dmax*2^31 < p_ntt/2 (the
+ * exactness bound of the transform; for N = 2048 the b_r are split in two
+ * 16-bit halves internally, as the blind rotation does). */
+FS_API int fs_ntt_polymul(fs_ctx* ctx, uint32_t N, uint32_t R, int32_t dmax, const int32_t* d,
+                   const uint32_t* b, uint32_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHESNN_H */

@@ -1,0 +1,548 @@
+// extern "C" boundary of libfhesnn (declared in include/fhesnn.h): argument
+// checking, error reporting, device-resident keys, NTT tables, the test
+// polynomial cache and scratch management around the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fs_internal.h"
+#include "kernels.h"
+
+// ------------------------------------------------------------------ handles
+
+struct fs_secret : fs::Secret {};
+struct fs_evk : fs::EvalKey {};
+
+struct fs_devkey {
+  fs_params prm{};
+  int device = 0;
+  double* bsk = nullptr;    // NTT domain, see launch_bsk_to_ntt
+  uint32_t* ksk = nullptr;  // [N][t][base-1][n+1]
+  double* fwd_tw = nullptr;
+  double* inv_tw = nullptr;
+  double* post = nullptr;
+  size_t bytes = 0;
+};
+
+struct fs_ctx {
+  int device = 0;
+  std::mutex mu;
+  uint32_t* ext = nullptr;  // extracted samples between blind rotation and key switch
+  size_t ext_words = 0;
+  // test polynomials on the device, keyed by (N, p, residue table)
+  std::map<std::vector<int32_t>, uint32_t*> tpoly;
+  // NTT tables per ring degree for fs_ntt_polymul
+  std::map<uint32_t, double*> tables;
+};
+
+namespace fs {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FS_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int launch_rc(int rc, const char* what) {
+  if (rc == 0) return FS_OK;
+  if (rc < 0) return fail(FS_ENOTSUP, std::string(what) + ": unsupported ring degree");
+  return fail(FS_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)rc));
+}
+
+// ---- NTT tables (exact integer arithmetic on the host)
+
+using u128 = unsigned __int128;
+constexpr uint64_t kPr = 0x6000000100001ull;  // same prime as the device transform
+
+uint64_t mulm(uint64_t a, uint64_t b) { return (uint64_t)((u128)a * b % kPr); }
+uint64_t powm(uint64_t a, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = mulm(r, a);
+    a = mulm(a, a);
+    e >>= 1;
+  }
+  return r;
+}
+double centred(uint64_t v) { return v > kPr / 2 ? -(double)(kPr - v) : (double)v; }
+uint32_t bitrev(uint32_t k, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) r |= ((k >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// host tables: fwd [N] psi^{brv(k)}, inv [N/2] omega^{-e}, post [N] psi^{-j} N^{-1}
+void ntt_tables(uint32_t N, std::vector<double>& fwd, std::vector<double>& inv,
+                std::vector<double>& post) {
+  const uint32_t logn = ilog2(N);
+  uint64_t psi = 0;
+  for (uint64_t x = 2;; ++x) {  // smallest x whose (P-1)/2N power has order 2N
+    psi = powm(x, (kPr - 1) / (2ull * N));
+    if (powm(psi, N) == kPr - 1) break;
+  }
+  const uint64_t psi_inv = powm(psi, kPr - 2);
+  const uint64_t omega_inv = mulm(psi_inv, psi_inv);
+  const uint64_t n_inv = powm(N, kPr - 2);
+  fwd.assign(N, 0.0);
+  for (uint32_t k = 1; k < N; ++k) fwd[k] = centred(powm(psi, bitrev(k, logn)));
+  inv.assign(N / 2, 0.0);
+  for (uint32_t e = 0; e < N / 2; ++e) inv[e] = centred(powm(omega_inv, e));
+  post.assign(N, 0.0);
+  for (uint32_t j = 0; j < N; ++j) post[j] = centred(mulm(powm(psi_inv, j), n_inv));
+}
+
+int upload_tables(uint32_t N, double** d_fwd, double** d_inv, double** d_post) {
+  std::vector<double> f, i, p;
+  ntt_tables(N, f, i, p);
+  double* buf = nullptr;
+  const size_t total = f.size() + i.size() + p.size();
+  FS_HIP(hipMalloc(&buf, total * sizeof(double)));
+  hipError_t e = hipMemcpy(buf, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(buf + f.size(), i.data(), i.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(buf + f.size() + i.size(), p.data(), p.size() * sizeof(double),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(buf);
+    return hip_fail(e, "upload NTT tables");
+  }
+  *d_fwd = buf;
+  *d_inv = buf + f.size();
+  *d_post = buf + f.size() + i.size();
+  return FS_OK;
+}
+
+int check_params(const fs_params* p) {
+  if (!p) return fail(FS_EINVAL, "null fs_params");
+  std::string why;
+  if (!params_supported(*p, &why)) return fail(FS_ENOTSUP, why);
+  return FS_OK;
+}
+
+int ensure_ext(fs_ctx* ctx, size_t words) {
+  if (ctx->ext_words >= words) return FS_OK;
+  if (ctx->ext) FS_HIP(hipFree(ctx->ext));
+  ctx->ext = nullptr;
+  ctx->ext_words = 0;
+  FS_HIP(hipMalloc(&ctx->ext, words * sizeof(uint32_t)));
+  ctx->ext_words = words;
+  return FS_OK;
+}
+
+// device test polynomial of a residue table (cached per context)
+int get_tpoly(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f, uint32_t** out) {
+  std::vector<int32_t> key(f, f + p);
+  key.push_back((int32_t)N);
+  key.push_back((int32_t)p);
+  auto it = ctx->tpoly.find(key);
+  if (it != ctx->tpoly.end()) {
+    *out = it->second;
+    return FS_OK;
+  }
+  std::vector<uint32_t> v(N);
+  int rc = test_poly(N, p, f, v.data());
+  if (rc) return rc;
+  uint32_t* d = nullptr;
+  FS_HIP(hipMalloc(&d, N * sizeof(uint32_t)));
+  hipError_t e = hipMemcpy(d, v.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "upload test polynomial");
+  }
+  ctx->tpoly.emplace(std::move(key), d);
+  *out = d;
+  return FS_OK;
+}
+
+// blind rotation of jobs = B * nlut, then key switch (or not)
+int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nlut,
+            const uint32_t* in, size_t B, uint32_t* out0, uint32_t* out1,
+            const uint32_t plain_add[2], int keyswitch, hipStream_t st) {
+  const fs_params& P = dk->prm;
+  const size_t jobs = B * nlut;
+  uint32_t* ext = nullptr;
+  if (keyswitch) {
+    int rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
+    if (rc) return rc;
+    ext = ctx->ext;
+  } else {
+    ext = out0;
+  }
+  BrArgs br{in, tp[0], nlut == 2 ? tp[1] : tp[0], nlut, P.n, dk->bsk, dk->fwd_tw,
+            dk->inv_tw, dk->post, ext};
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, st), "blind rotation");
+  if (rc || !keyswitch) return rc;
+  KsArgs ks{};
+  ks.in = ext;
+  ks.ksk = dk->ksk;
+  ks.out0 = out0;
+  ks.out1 = out1;
+  ks.plain_add[0] = plain_add[0];
+  ks.plain_add[1] = plain_add[1];
+  ks.nlut = nlut;
+  ks.n = P.n;
+  ks.N = P.N;
+  ks.t = P.ks_t;
+  ks.beta = P.ks_base_bit;
+  return launch_rc(launch_keyswitch(ks, jobs, st), "key switch");
+}
+
+}  // namespace
+}  // namespace fs
+
+using namespace fs;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* fs_last_error(void) { return g_err.c_str(); }
+
+int fs_params_default(int shape, fs_params* out) {
+  if (!out) return fail(FS_EINVAL, "null output");
+  fs_params p{};
+  p.n = 630;
+  p.k = 1;
+  p.ks_t = 8;
+  p.ks_base_bit = 2;
+  p.sigma_lwe = 0x1p-15;
+  p.sigma_ksk = 0x1p-15;
+  p.version = FS_PARAMS_VERSION;
+  if (shape == 0) {
+    p.N = 1024; p.l = 3; p.bg_bit = 7; p.p = 32; p.sigma_bsk = 0x1p-25;
+  } else if (shape == 1) {
+    p.N = 2048; p.l = 2; p.bg_bit = 10; p.p = 64; p.sigma_bsk = 0x1p-31;
+  } else {
+    return fail(FS_EINVAL, "shape must be 0 or 1");
+  }
+  *out = p;
+  return FS_OK;
+}
+
+int fs_keygen(const fs_params* params, uint64_t seed, fs_secret** sk, fs_evk** evk) {
+  if (!sk || !evk) return fail(FS_EINVAL, "null output handle");
+  int rc = check_params(params);
+  if (rc) return rc;
+  try {
+    Secret* s = nullptr;
+    EvalKey* e = nullptr;
+    rc = keygen(*params, seed, &s, &e);
+    if (rc) return rc;
+    auto* so = new fs_secret;
+    static_cast<Secret&>(*so) = std::move(*s);
+    auto* eo = new fs_evk;
+    static_cast<EvalKey&>(*eo) = std::move(*e);
+    delete s;
+    delete e;
+    *sk = so;
+    *evk = eo;
+    return FS_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FS_ENOMEM, "fs_keygen: out of host memory");
+  }
+}
+
+int fs_encrypt(const fs_secret* sk, const int32_t* m, size_t count, uint64_t seed,
+               uint64_t first_index, uint32_t* ct_out) {
+  if (!sk || (count && (!m || !ct_out))) return fail(FS_EINVAL, "fs_encrypt: null argument");
+  encrypt(*sk, m, count, seed, first_index, ct_out);
+  return FS_OK;
+}
+
+int fs_decrypt(const fs_secret* sk, const uint32_t* ct, size_t count, uint32_t dim,
+               int32_t* m_out) {
+  if (!sk || (count && (!ct || !m_out))) return fail(FS_EINVAL, "fs_decrypt: null argument");
+  return decrypt(*sk, ct, count, dim, m_out);
+}
+
+int fs_secret_export(const fs_secret* sk, int32_t* s, int32_t* z) {
+  if (!sk) return fail(FS_EINVAL, "null secret");
+  if (s) std::memcpy(s, sk->s.data(), sk->s.size() * sizeof(int32_t));
+  if (z) std::memcpy(z, sk->z.data(), sk->z.size() * sizeof(int32_t));
+  return FS_OK;
+}
+
+int fs_evk_export(const fs_evk* evk, uint32_t* bsk, uint32_t* ksk) {
+  if (!evk) return fail(FS_EINVAL, "null evaluation key");
+  if (bsk) std::memcpy(bsk, evk->bsk.data(), evk->bsk.size() * sizeof(uint32_t));
+  if (ksk) std::memcpy(ksk, evk->ksk.data(), evk->ksk.size() * sizeof(uint32_t));
+  return FS_OK;
+}
+
+int fs_evk_params(const fs_evk* evk, fs_params* out) {
+  if (!evk || !out) return fail(FS_EINVAL, "null argument");
+  *out = evk->prm;
+  return FS_OK;
+}
+
+void fs_secret_free(fs_secret* sk) { delete sk; }
+void fs_evk_free(fs_evk* evk) { delete evk; }
+
+int fs_test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v_out) {
+  if (!f || !v_out) return fail(FS_EINVAL, "fs_test_poly: null argument");
+  if (N < 2 || (N & (N - 1)) || p < 2 || (p & (p - 1)) || p > 2 * N)
+    return fail(FS_EINVAL, "fs_test_poly: N and p must be powers of two with p <= 2N");
+  return test_poly(N, p, f, v_out);
+}
+
+int fs_lif_luts(const fs_lif* lif, uint32_t p, int32_t* fire, int32_t* reset) {
+  if (!lif) return fail(FS_EINVAL, "null fs_lif");
+  if (p < 4 || (p & (p - 1))) return fail(FS_EINVAL, "p must be a power of two >= 4");
+  if (lif->v_th <= 0 || lif->v_th > (int32_t)(p / 2))
+    return fail(FS_EINVAL, "v_th must be in 1..p/2");
+  if (lif->tau == 1) return fail(FS_EINVAL, "tau must be 0 (IF) or >= 2");
+  lif_luts(*lif, p, fire, reset);
+  return FS_OK;
+}
+
+int fs_lif_range_check(const fs_lif* lif, uint32_t p, const int32_t* W, size_t O, size_t I,
+                       int32_t x_lo, int32_t x_hi, int64_t* m_out) {
+  if (!lif || !W || !m_out) return fail(FS_EINVAL, "fs_lif_range_check: null argument");
+  const int64_t xa = std::max<int64_t>(x_lo < 0 ? -(int64_t)x_lo : x_lo,
+                                       x_hi < 0 ? -(int64_t)x_hi : x_hi);
+  int64_t worst = 0;
+  for (size_t o = 0; o < O; ++o) {
+    int64_t s = 0;
+    for (size_t i = 0; i < I; ++i) s += (W[o * I + i] < 0 ? -(int64_t)W[o * I + i] : W[o * I + i]);
+    worst = std::max(worst, s * xa);
+  }
+  *m_out = (int64_t)lif->v_th + worst;
+  return *m_out <= (int64_t)(p / 2) ? FS_OK : 1;
+}
+
+int fs_ctx_create(int device, fs_ctx** ctx) {
+  if (!ctx) return fail(FS_EINVAL, "null output handle");
+  int count = 0;
+  FS_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(FS_EINVAL, "no such HIP device");
+  auto* c = new fs_ctx;
+  c->device = device;
+  *ctx = c;
+  return FS_OK;
+}
+
+int fs_ctx_destroy(fs_ctx* ctx) {
+  if (!ctx) return FS_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->ext) (void)hipFree(ctx->ext);
+  for (auto& kv : ctx->tpoly) (void)hipFree(kv.second);
+  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
+  delete ctx;
+  return FS_OK;
+}
+
+int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  return ensure_ext(ctx, max_jobs * (size_t)(N + 1));
+}
+
+int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
+  if (!ctx || !evk || !dk_out) return fail(FS_EINVAL, "fs_evk_upload: null argument");
+  int rc = check_params(&evk->prm);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  const fs_params& P = evk->prm;
+  const uint32_t limbs = P.N == 2048 ? 2 : 1;
+  auto* dk = new fs_devkey;
+  dk->prm = P;
+  dk->device = ctx->device;
+  uint32_t* coef = nullptr;
+  auto cleanup = [&](int code) {
+    if (coef) (void)hipFree(coef);
+    fs_devkey_free(dk);
+    return code;
+  };
+  const size_t bsk_words = evk->bsk.size();
+  const size_t bsk_ntt = bsk_words * limbs;  // doubles
+  hipError_t e = hipMalloc(&dk->bsk, bsk_ntt * sizeof(double));
+  if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: BSK allocation failed"));
+  e = hipMalloc(&dk->ksk, evk->ksk.size() * sizeof(uint32_t));
+  if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
+  e = hipMalloc(&coef, bsk_words * sizeof(uint32_t));
+  if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: staging allocation failed"));
+  rc = upload_tables(P.N, &dk->fwd_tw, &dk->inv_tw, &dk->post);
+  if (rc) return cleanup(rc);
+  e = hipMemcpy(coef, evk->bsk.data(), bsk_words * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(dk->ksk, evk->ksk.data(), evk->ksk.size() * sizeof(uint32_t),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: copy"));
+  rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
+                 "BSK conversion");
+  if (rc) return cleanup(rc);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: conversion"));
+  (void)hipFree(coef);
+  coef = nullptr;
+  dk->bytes = bsk_ntt * sizeof(double) + evk->ksk.size() * sizeof(uint32_t) +
+              (size_t)(5 * P.N / 2) * sizeof(double);
+  *dk_out = dk;
+  return FS_OK;
+}
+
+int fs_devkey_params(const fs_devkey* dk, fs_params* out) {
+  if (!dk || !out) return fail(FS_EINVAL, "null argument");
+  *out = dk->prm;
+  return FS_OK;
+}
+
+size_t fs_devkey_bytes(const fs_devkey* dk) { return dk ? dk->bytes : 0; }
+
+void fs_devkey_free(fs_devkey* dk) {
+  if (!dk) return;
+  DeviceGuard g(dk->device);
+  if (dk->bsk) (void)hipFree(dk->bsk);
+  if (dk->ksk) (void)hipFree(dk->ksk);
+  if (dk->fwd_tw) (void)hipFree(dk->fwd_tw);  // one allocation holds all three tables
+  delete dk;
+}
+
+int fs_lwe_linear(fs_ctx* ctx, const int32_t* W, size_t O, size_t I, uint32_t dim,
+                  const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream) {
+  if (!ctx || (O && (!W || !y)) || (O && I && !x) || dim == 0)
+    return fail(FS_EINVAL, "fs_lwe_linear: null argument or zero width");
+  if (O > 0xFFFFFFFFu || I > 0xFFFFFFFFu) return fail(FS_EINVAL, "fs_lwe_linear: shape too large");
+  DeviceGuard g(ctx->device);
+  return launch_rc(launch_lwe_linear(W, O, I, dim, x, add, y, as_stream(stream)), "lwe_linear");
+}
+
+int fs_lwe_conv2d(fs_ctx* ctx, const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd,
+                  uint32_t Co, uint32_t K, uint32_t stride, uint32_t pad, uint32_t dim,
+                  const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream) {
+  if (!ctx || !W || !x || !y || dim == 0) return fail(FS_EINVAL, "fs_lwe_conv2d: null argument");
+  if (Ci == 0 || Co == 0 || K == 0 || stride == 0 || H + 2 * pad < K || Wd + 2 * pad < K)
+    return fail(FS_EINVAL, "fs_lwe_conv2d: bad geometry");
+  const uint64_t Ho = (H + 2 * pad - K) / stride + 1, Wo = (Wd + 2 * pad - K) / stride + 1;
+  if ((uint64_t)Co * Ho * Wo > 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_lwe_conv2d: too many outputs");
+  DeviceGuard g(ctx->device);
+  return launch_rc(launch_lwe_conv2d(W, Ci, H, Wd, Co, K, stride, pad, dim, x, add, y,
+                                     as_stream(stream)), "lwe_conv2d");
+}
+
+int fs_lwe_add(fs_ctx* ctx, const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
+               void* stream) {
+  if (!ctx || (words && (!a || !b || !y))) return fail(FS_EINVAL, "fs_lwe_add: null argument");
+  if (words / 256 >= 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_lwe_add: too many words");
+  DeviceGuard g(ctx->device);
+  return launch_rc(launch_lwe_add(a, b, words, y, as_stream(stream)), "lwe_add");
+}
+
+int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const uint32_t* in, size_t B,
+           uint32_t* out, int keyswitch, void* stream) {
+  if (!ctx || !dk || !lut || (B && (!in || !out))) return fail(FS_EINVAL, "fs_pbs: null argument");
+  if (dk->device != ctx->device) return fail(FS_EPARAM, "fs_pbs: key lives on another device");
+  if (B > 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_pbs: batch too large");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  int rc = get_tpoly(ctx, dk->prm.N, dk->prm.p, lut, &tp[0]);
+  if (rc) return rc;
+  const uint32_t zero[2] = {0u, 0u};
+  return run_pbs(ctx, dk, tp, 1, in, B, out, nullptr, zero, keyswitch, as_stream(stream));
+}
+
+int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
+               uint32_t* spike2_out, uint32_t* v_out, void* stream) {
+  if (!ctx || !dk || !lif || (B && (!h || !spike2_out || !v_out)))
+    return fail(FS_EINVAL, "fs_pbs_lif: null argument");
+  if (dk->device != ctx->device) return fail(FS_EPARAM, "fs_pbs_lif: key lives on another device");
+  if (B > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif: batch too large");
+  const uint32_t p = dk->prm.p;
+  std::vector<int32_t> fire(p), reset(p);
+  int rc = fs_lif_luts(lif, p, fire.data(), reset.data());
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  rc = get_tpoly(ctx, dk->prm.N, p, fire.data(), &tp[0]);
+  if (rc) return rc;
+  rc = get_tpoly(ctx, dk->prm.N, p, reset.data(), &tp[1]);
+  if (rc) return rc;
+  const uint32_t add[2] = {delta_of(p), 0u};  // 2S = bootstrap_Fire + 1
+  return run_pbs(ctx, dk, tp, 2, h, B, spike2_out, v_out, add, 1, as_stream(stream));
+}
+
+int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,
+                 void* stream) {
+  if (!ctx || !dk || (B && (!in || !out))) return fail(FS_EINVAL, "fs_keyswitch: null argument");
+  if (B > 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_keyswitch: batch too large");
+  DeviceGuard g(ctx->device);
+  const fs_params& P = dk->prm;
+  KsArgs ks{};
+  ks.in = in;
+  ks.ksk = dk->ksk;
+  ks.out0 = out;
+  ks.out1 = nullptr;
+  ks.nlut = 1;
+  ks.n = P.n;
+  ks.N = P.N;
+  ks.t = P.ks_t;
+  ks.beta = P.ks_base_bit;
+  return launch_rc(launch_keyswitch(ks, B, as_stream(stream)), "key switch");
+}
+
+int fs_ntt_polymul(fs_ctx* ctx, uint32_t N, uint32_t R, int32_t dmax, const int32_t* d,
+                   const uint32_t* b, uint32_t* out, void* stream) {
+  if (!ctx || !d || !b || !out || R == 0 || dmax <= 0)
+    return fail(FS_EINVAL, "fs_ntt_polymul: null argument or empty product");
+  if (N != 1024 && N != 2048) return fail(FS_ENOTSUP, "fs_ntt_polymul: N must be 1024 or 2048");
+  const double coef = N == 2048 ? 32768.0 : 2147483648.0;  // 2^15 per half, or 2^31
+  if ((double)R * N * dmax * coef >= 844424930656256.0)
+    return fail(FS_EINVAL, "fs_ntt_polymul: R*N*dmax exceeds the exactness bound of the transform");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  auto it = ctx->tables.find(N);
+  double *f = nullptr, *iv = nullptr, *po = nullptr;
+  if (it == ctx->tables.end()) {
+    int rc = upload_tables(N, &f, &iv, &po);
+    if (rc) return rc;
+    ctx->tables[N] = f;
+  } else {
+    f = it->second;
+  }
+  iv = f + N;
+  po = f + N + N / 2;
+  return launch_rc(launch_polymul(N, d, b, R, out, f, iv, po, as_stream(stream)), "polymul");
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Kernel argument blocks and launchers (internal to libfhesnn).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fs {
+
+struct BrArgs {
+  const uint32_t* in;     // [B][n+1] input samples under s
+  const uint32_t* tpoly0; // [N] test polynomial of program function 0
+  const uint32_t* tpoly1; // [N] test polynomial of program function 1
+  uint32_t nlut;          // job j bootstraps sample j / nlut with function j % nlut
+  uint32_t n;
+  const double* bsk;      // NTT-domain bootstrapping key
+  const double* fwd_tw;   // [N] psi^{brv(k)}
+  const double* inv_tw;   // [N/2] omega^{-e}
+  const double* post;     // [N] psi^{-j} N^{-1}
+  uint32_t* ext;          // [jobs][N+1] extracted samples under z
+};
+
+struct KsArgs {
+  const uint32_t* in;  // [jobs][N+1]
+  const uint32_t* ksk; // [N][t][base-1][n+1]
+  uint32_t* out0;      // program function 0 outputs, [jobs/nlut][n+1]
+  uint32_t* out1;      // program function 1 outputs (nlut == 2)
+  uint32_t plain_add[2];  // Delta * c added to b per program function
+  uint32_t nlut, n, N, t, beta;
+};
+
+int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
+                      const double* tw, hipStream_t st);
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, hipStream_t st);
+int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
+int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
+                   const double* tw, const double* itw, const double* post, hipStream_t st);
+
+int launch_lwe_linear(const int32_t* W, size_t O, size_t I, uint32_t dim, const uint32_t* x,
+                      const uint32_t* add, uint32_t* y, hipStream_t st);
+int launch_lwe_conv2d(const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd, uint32_t Co,
+                      uint32_t K, uint32_t stride, uint32_t pad, uint32_t dim,
+                      const uint32_t* x, const uint32_t* add, uint32_t* y, hipStream_t st);
+int launch_lwe_add(const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
+                   hipStream_t st);
+
+}  // namespace fs

@@ -1,0 +1,114 @@
+// WeightSum on LWE ciphertexts (Sec. 4.1, Eq. "noise grows"): plaintext
+// integer weights times ciphertexts, summed word by word mod 2^32, for
+// fully connected and convolutional layers, plus the homomorphic addition
+// that forms H = V + I (Theorem 3.1, Eq. DiscretEquation).
+//
+// These layers are integer contractions with tiny weights (|w| <= 15 in
+// the workloads) and move far fewer operations than the bootstrappings
+// they feed; they run on the vector ALUs with coalesced ciphertext rows.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace fs {
+
+// y[o][w] = add[o][w] + sum_i W[o][i] x[i][w].  Block: 256 words w of OT
+// consecutive outputs o; each x word loaded once feeds OT products.  W
+// reads are uniform across the block (scalar loads).
+template <int OT>
+__global__ void __launch_bounds__(256)
+lwe_linear_kernel(const int32_t* __restrict__ W, uint32_t O, uint32_t I, uint32_t dim,
+                  const uint32_t* __restrict__ x, const uint32_t* add, uint32_t* y) {
+  const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t o0 = blockIdx.y * OT;
+  uint32_t acc[OT];
+#pragma unroll
+  for (int k = 0; k < OT; ++k) acc[k] = 0u;
+  const bool live = w < dim;
+  const uint32_t wc = live ? w : 0;
+  for (uint32_t i = 0; i < I; ++i) {
+    const uint32_t xv = x[(size_t)i * dim + wc];
+#pragma unroll
+    for (int k = 0; k < OT; ++k) {
+      const uint32_t o = o0 + k < O ? o0 + k : O - 1;
+      acc[k] += (uint32_t)W[(size_t)o * I + i] * xv;
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < OT; ++k) {
+    const uint32_t o = o0 + k;
+    if (o < O) {
+      const size_t idx = (size_t)o * dim + w;
+      y[idx] = acc[k] + (add ? add[idx] : 0u);
+    }
+  }
+}
+
+// Convolution: block = 256 words of one output position (co, oy, ox).
+__global__ void __launch_bounds__(256)
+lwe_conv2d_kernel(const int32_t* __restrict__ W, uint32_t Ci, uint32_t H, uint32_t Wd,
+                  uint32_t K, uint32_t stride, uint32_t pad, uint32_t Ho, uint32_t Wo,
+                  uint32_t dim, const uint32_t* __restrict__ x, const uint32_t* add,
+                  uint32_t* y) {
+  const uint32_t w = blockIdx.y * 256 + threadIdx.x;
+  const uint32_t o = blockIdx.x;  // (co*Ho + oy)*Wo + ox
+  if (w >= dim) return;
+  const uint32_t ox = o % Wo, oy = (o / Wo) % Ho, co = o / (Wo * Ho);
+  uint32_t acc = 0u;
+  for (uint32_t ci = 0; ci < Ci; ++ci)
+    for (uint32_t ky = 0; ky < K; ++ky) {
+      const int iy = (int)(oy * stride + ky) - (int)pad;
+      if (iy < 0 || iy >= (int)H) continue;
+      for (uint32_t kx = 0; kx < K; ++kx) {
+        const int ix = (int)(ox * stride + kx) - (int)pad;
+        if (ix < 0 || ix >= (int)Wd) continue;
+        const uint32_t wt = (uint32_t)W[((co * Ci + ci) * K + ky) * K + kx];
+        acc += wt * x[(((size_t)ci * H + iy) * Wd + ix) * dim + w];
+      }
+    }
+  const size_t idx = (size_t)o * dim + w;
+  y[idx] = acc + (add ? add[idx] : 0u);
+}
+
+__global__ void __launch_bounds__(256)
+lwe_add_kernel(const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < words) y[i] = a[i] + b[i];
+}
+
+#define FS_LAUNCH_CHECK()                 \
+  do {                                    \
+    hipError_t e_ = hipGetLastError();    \
+    if (e_ != hipSuccess) return (int)e_; \
+  } while (0)
+
+int launch_lwe_linear(const int32_t* W, size_t O, size_t I, uint32_t dim, const uint32_t* x,
+                      const uint32_t* add, uint32_t* y, hipStream_t st) {
+  if (O == 0) return 0;
+  constexpr int OT = 8;
+  dim3 g((dim + 255) / 256, (uint32_t)((O + OT - 1) / OT));
+  lwe_linear_kernel<OT><<<g, 256, 0, st>>>(W, (uint32_t)O, (uint32_t)I, dim, x, add, y);
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_lwe_conv2d(const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd, uint32_t Co,
+                      uint32_t K, uint32_t stride, uint32_t pad, uint32_t dim,
+                      const uint32_t* x, const uint32_t* add, uint32_t* y, hipStream_t st) {
+  const uint32_t Ho = (H + 2 * pad - K) / stride + 1, Wo = (Wd + 2 * pad - K) / stride + 1;
+  dim3 g(Co * Ho * Wo, (dim + 255) / 256);
+  lwe_conv2d_kernel<<<g, 256, 0, st>>>(W, Ci, H, Wd, K, stride, pad, Ho, Wo, dim, x, add, y);
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_lwe_add(const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
+                   hipStream_t st) {
+  if (words == 0) return 0;
+  lwe_add_kernel<<<dim3((uint32_t)((words + 255) / 256)), 256, 0, st>>>(a, b, words, y);
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace fs

@@ -1,0 +1,313 @@
+// Programmable bootstrapping on gfx950: BSK conversion to the NTT domain,
+// blind rotation with fused initialisation and sample extraction, key
+// switching with the LIF epilogue, and an NTT polynomial-product check.
+//
+// Sec. 2.1, Theorem 2.1 and the four steps after it (Initialization, Blind
+// Rotation, Sample Extraction, Key Switching); Sec. 4.2 (FHE-Fire adds 1
+// after bootstrapping).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "ntt_fp64.h"
+
+namespace fs {
+
+// ---------------------------------------------------------------------------
+// BSK: coefficient domain [n][rows][2][N] (Torus32) -> NTT domain, layout
+// [n][rows][16][TP][2 * limbs] doubles, so that in the blind rotation thread
+// t of the polynomial reads, for register r, one contiguous group of
+// 2*limbs values (mask and body product of digit row `row`).
+// limbs = 1: the centred 32-bit coefficient; limbs = 2: its low and high
+// signed 16-bit halves (coefficient = lo + 2^16 hi).
+template <int LOGN, int LIMBS>
+__global__ void __launch_bounds__(NttShape<LOGN>::TP)
+bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, uint32_t rows,
+                  const double* __restrict__ tw) {
+  using S = NttShape<LOGN>;
+  __shared__ double lds[S::LDS_DOUBLES];
+  const int t = threadIdx.x;
+  const uint32_t poly = blockIdx.x;       // (i*rows + row)*2 + o
+  const uint32_t limb = blockIdx.y;       // < LIMBS
+  const uint32_t o = poly & 1, irow = poly >> 1;
+  const uint32_t* src = bsk + (size_t)poly * S::N;
+  double x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int32_t c = (int32_t)src[t + S::TP * r];
+    if (LIMBS == 1) {
+      x[r] = (double)c;
+    } else {
+      const int32_t lo = (int32_t)(int16_t)(uint16_t)(uint32_t)c;
+      const int32_t hi = (c - lo) >> 16;
+      x[r] = (double)(limb == 0 ? lo : hi);
+    }
+  }
+  ntt_fwd<LOGN>(x, lds, tw, t);
+  double* dst = out + (size_t)irow * 16 * S::TP * 2 * LIMBS;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) dst[((size_t)r * S::TP + t) * 2 * LIMBS + o * LIMBS + limb] = x[r];
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation.  One workgroup of TP threads per job (ciphertext, test
+// polynomial); the accumulator lives in LDS in natural order for all n
+// CMux steps.  Step i (a~ = a~_i != 0):
+//   D_c = X^{a~} ACC_c - ACC_c (c = 0 mask, 1 body)
+//   for each gadget level j: digit polynomial -> forward NTT -> multiply by
+//       the two NTT-domain TGSW_i row entries and accumulate
+//   inverse NTT of the two accumulators -> exact integers -> ACC_c +=
+// Initialization ACC = (0, X^{-b~} v) and sample extraction of
+// coefficient 0 are fused at both ends.
+template <int LOGN, int L, int BG, int LIMBS>
+__global__ void __launch_bounds__(NttShape<LOGN>::TP)
+blind_rotate_kernel(BrArgs a) {
+  using S = NttShape<LOGN>;
+  constexpr int N = S::N, TP = S::TP, ROWS = 2 * L;
+  constexpr uint32_t HALF = 1u << (BG - 1), MASK = (1u << BG) - 1;
+  constexpr uint32_t NU = LOGN + 1;  // log2(2N)
+  __shared__ double lds[S::LDS_DOUBLES];
+  __shared__ uint32_t acc[2][N];
+
+  const int t = threadIdx.x;
+  const size_t job = blockIdx.x;
+  const uint32_t n = a.n;
+  const uint32_t* ct = a.in + (job / a.nlut) * (size_t)(n + 1);
+  const uint32_t* v = (job % a.nlut) == 0 ? a.tpoly0 : a.tpoly1;
+
+  // gadget rounding offset: sum_{j=1..L} (Bg/2) 2^{32 - j BG} + 2^{31 - L BG}
+  uint32_t off = 1u << (31 - L * BG);
+#pragma unroll
+  for (int j = 1; j <= L; ++j) off += HALF << (32 - j * BG);
+
+  // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
+  {
+    const uint32_t bbar = (ct[n] + (1u << (31 - NU))) >> (32 - NU);
+    const uint32_t e = (2 * N - bbar) & (2 * N - 1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int j = t + TP * r;
+      // (X^e v)_j = v_{j-e} with sign (-1)^{number of wraps past N}
+      int src = j - (int)e;
+      uint32_t val;
+      if (src >= 0) val = v[src];
+      else if (src + N >= 0) val = 0u - v[src + N];
+      else val = v[src + 2 * N];
+      acc[0][j] = 0u;
+      acc[1][j] = val;
+    }
+  }
+  __syncthreads();
+
+  const double* __restrict__ bsk = a.bsk;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t abar = (ct[i] + (1u << (31 - NU))) >> (32 - NU);
+    if (abar == 0) continue;  // X^0 ACC - ACC = 0: every digit is zero
+    double p0[LIMBS][16], p1[LIMBS][16];
+#pragma unroll
+    for (int lb = 0; lb < LIMBS; ++lb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { p0[lb][r] = 0.0; p1[lb][r] = 0.0; }
+
+    const double* bsk_i = bsk + (size_t)i * ROWS * 16 * TP * 2 * LIMBS;
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+      uint32_t d[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int j = t + TP * r;
+        int src = j - (int)abar;
+        uint32_t rot;
+        if (src >= 0) rot = acc[c][src];
+        else if (src + N >= 0) rot = 0u - acc[c][src + N];
+        else rot = acc[c][src + 2 * N];
+        d[r] = rot - acc[c][j] + off;
+      }
+#pragma unroll 1
+      for (int lv = 0; lv < L; ++lv) {
+        double x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          x[r] = (double)((int32_t)((d[r] >> (32 - (lv + 1) * BG)) & MASK) - (int32_t)HALF);
+        ntt_fwd<LOGN>(x, lds, a.fwd_tw, t);
+        const double* row = bsk_i + (size_t)(c * L + lv) * 16 * TP * 2 * LIMBS;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double* g = row + ((size_t)r * TP + t) * 2 * LIMBS;
+#pragma unroll
+          for (int lb = 0; lb < LIMBS; ++lb) {
+            p0[lb][r] += mulmod(x[r], g[lb]);
+            p1[lb][r] += mulmod(x[r], g[LIMBS + lb]);
+          }
+        }
+      }
+    }
+    // inverse transforms; p* hold sums of 2L products, each < 0.65 P
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t upd[16];
+#pragma unroll
+      for (int lb = 0; lb < LIMBS; ++lb) {
+        double* y = c == 0 ? p0[lb] : p1[lb];
+        ntt_inv<LOGN>(y, lds, a.inv_tw, a.post, t);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t part = low32(y[r]);
+          upd[r] = lb == 0 ? part : upd[r] + (part << 16);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][t + TP * r] += upd[r];
+    }
+    __syncthreads();
+  }
+
+  // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
+  uint32_t* out = a.ext + job * (size_t)(N + 1);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j = t + TP * r;
+    out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
+  }
+  if (t == 0) out[N] = acc[1][0];
+}
+
+// ---------------------------------------------------------------------------
+// Key switching z -> s with the bootstrapping epilogue.  Thread w owns
+// output word w of one sample.  out = (0, b') - sum over coefficients i and
+// digits j of KSK[i][j][d_ij - 1] (d_ij != 0), where a'_i is rounded to
+// t*beta bits and split into base-2^beta digits, most significant first.
+// Sample m is job (ciphertext m / nlut, program function m % nlut); its
+// result goes to out[m % nlut] at row m / nlut, and plain_add[m % nlut] is
+// added to b (FHE-Fire adds Delta * 1 after bootstrapping).
+__global__ void __launch_bounds__(256)
+keyswitch_kernel(KsArgs a) {
+  const uint32_t w = blockIdx.y * 256 + threadIdx.x;
+  const size_t m = blockIdx.x;
+  const uint32_t n = a.n, N = a.N, t = a.t, beta = a.beta, base1 = (1u << beta) - 1;
+  const uint32_t prec = t * beta;
+  if (w > n) return;
+  const uint32_t* in = a.in + m * (size_t)(N + 1);
+  const uint32_t lut = (uint32_t)(m % a.nlut);
+  uint32_t r = w == n ? in[N] + a.plain_add[lut] : 0u;
+  const size_t stride = (size_t)(n + 1);
+  const uint32_t* ksk = a.ksk + w;
+  for (uint32_t i = 0; i < N; ++i) {
+    const uint32_t abar = (in[i] + (1u << (31 - prec))) >> (32 - prec);
+    const uint32_t* rows = ksk + (size_t)i * t * base1 * stride;
+    for (uint32_t j = 0; j < t; ++j) {
+      const uint32_t dg = (abar >> ((t - 1 - j) * beta)) & base1;
+      if (dg) r -= rows[((size_t)j * base1 + (dg - 1)) * stride];
+    }
+  }
+  uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * stride;
+  out[w] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Negacyclic product check: out = sum_r d_r b_r through the same transform.
+template <int LOGN, int LIMBS>
+__global__ void __launch_bounds__(NttShape<LOGN>::TP)
+polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, uint32_t R,
+               uint32_t* __restrict__ out, const double* __restrict__ tw,
+               const double* __restrict__ itw, const double* __restrict__ post) {
+  using S = NttShape<LOGN>;
+  __shared__ double lds[S::LDS_DOUBLES];
+  const int t = threadIdx.x;
+  double accv[LIMBS][16];
+#pragma unroll
+  for (int lb = 0; lb < LIMBS; ++lb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accv[lb][r] = 0.0;
+  for (uint32_t q = 0; q < R; ++q) {
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = (double)d[(size_t)q * S::N + t + S::TP * r];
+    ntt_fwd<LOGN>(x, lds, tw, t);
+#pragma unroll
+    for (int lb = 0; lb < LIMBS; ++lb) {
+      double y[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int32_t c = (int32_t)b[(size_t)q * S::N + t + S::TP * r];
+        if (LIMBS == 1) y[r] = (double)c;
+        else {
+          const int32_t lo = (int32_t)(int16_t)(uint16_t)(uint32_t)c;
+          y[r] = (double)(lb == 0 ? lo : (c - lo) >> 16);
+        }
+      }
+      ntt_fwd<LOGN>(y, lds, tw, t);
+      // y is in round-C mapping like x: pointwise products line up
+#pragma unroll
+      for (int r = 0; r < 16; ++r) accv[lb][r] = redc(accv[lb][r] + mulmod(x[r], y[r]));
+    }
+  }
+  uint32_t res[16];
+#pragma unroll
+  for (int lb = 0; lb < LIMBS; ++lb) {
+    ntt_inv<LOGN>(accv[lb], lds, itw, post, t);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t part = low32(accv[lb][r]);
+      res[r] = lb == 0 ? part : res[r] + (part << 16);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[t + S::TP * r] = res[r];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+#define FS_LAUNCH_CHECK()                                     \
+  do {                                                        \
+    hipError_t e_ = hipGetLastError();                        \
+    if (e_ != hipSuccess) return (int)e_;                     \
+  } while (0)
+
+int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
+                      const double* tw, hipStream_t st) {
+  const uint32_t rows = 2 * l;
+  if (N == 1024) {
+    dim3 g(n * rows * 2, 1);
+    bsk_to_ntt_kernel<10, 1><<<g, 64, 0, st>>>(bsk_coef, out, rows, tw);
+  } else if (N == 2048) {
+    dim3 g(n * rows * 2, 2);
+    bsk_to_ntt_kernel<11, 2><<<g, 128, 0, st>>>(bsk_coef, out, rows, tw);
+  } else {
+    return -1;
+  }
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, hipStream_t st) {
+  if (jobs == 0) return 0;
+  if (N == 1024) {
+    blind_rotate_kernel<10, 3, 7, 1><<<dim3((uint32_t)jobs), 64, 0, st>>>(a);
+  } else if (N == 2048) {
+    blind_rotate_kernel<11, 2, 10, 2><<<dim3((uint32_t)jobs), 128, 0, st>>>(a);
+  } else {
+    return -1;
+  }
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {
+  if (count == 0) return 0;
+  dim3 g((uint32_t)count, (a.n + 1 + 255) / 256);
+  keyswitch_kernel<<<g, 256, 0, st>>>(a);
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
+                   const double* tw, const double* itw, const double* post, hipStream_t st) {
+  if (N == 1024) polymul_kernel<10, 1><<<1, 64, 0, st>>>(d, b, R, out, tw, itw, post);
+  else if (N == 2048) polymul_kernel<11, 2><<<1, 128, 0, st>>>(d, b, R, out, tw, itw, post);
+  else return -1;
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace fs

@@ -1,0 +1,345 @@
+"""ctypes binding of libfhesnn (include/fhesnn.h): argument marshalling only.
+
+Every entry point keeps the C name without the ``fs_`` prefix.  Device
+buffers are torch tensors on a HIP device (int32 storage holding the uint32
+torus words); streams are torch streams.  Nothing here computes on
+ciphertexts: each call goes straight to the library, which must be built
+(``python -m paper_2309_09025_amd.build``); importing without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhesnn.so")
+
+FS_OK, FS_EINVAL, FS_ENOMEM, FS_EDEVICE, FS_EPARAM, FS_EBUDGET, FS_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+FS_PARAMS_VERSION = 1
+
+
+class FsError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("N", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("l", ctypes.c_uint32), ("bg_bit", ctypes.c_uint32), ("ks_t", ctypes.c_uint32),
+                ("ks_base_bit", ctypes.c_uint32), ("p", ctypes.c_uint32),
+                ("sigma_lwe", ctypes.c_double), ("sigma_bsk", ctypes.c_double),
+                ("sigma_ksk", ctypes.c_double), ("version", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class CLif(ctypes.Structure):
+    _fields_ = [("v_th", ctypes.c_int32), ("tau", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_sz = ctypes.c_size_t
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int32
+_int = ctypes.c_int
+_PP = ctypes.POINTER(CParams)
+_LP = ctypes.POINTER(CLif)
+
+# name -> (restype, argtypes); every symbol declared in include/fhesnn.h
+SIGNATURES = {
+    "fs_last_error": (ctypes.c_char_p, []),
+    "fs_params_default": (_int, [_int, _PP]),
+    "fs_keygen": (_int, [_PP, _u64, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "fs_encrypt": (_int, [_vp, _i32p, _sz, _u64, _u64, _u32p]),
+    "fs_decrypt": (_int, [_vp, _u32p, _sz, _u32, _i32p]),
+    "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
+    "fs_evk_export": (_int, [_vp, _u32p, _u32p]),
+    "fs_evk_params": (_int, [_vp, _PP]),
+    "fs_secret_free": (None, [_vp]),
+    "fs_evk_free": (None, [_vp]),
+    "fs_test_poly": (_int, [_u32, _u32, _i32p, _u32p]),
+    "fs_lif_luts": (_int, [_LP, _u32, _i32p, _i32p]),
+    "fs_lif_range_check": (_int, [_LP, _u32, _i32p, _sz, _sz, _i32, _i32, _i64p]),
+    "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
+    "fs_ctx_destroy": (_int, [_vp]),
+    "fs_ctx_reserve": (_int, [_vp, _u32, _sz]),
+    "fs_evk_upload": (_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "fs_devkey_params": (_int, [_vp, _PP]),
+    "fs_devkey_bytes": (_sz, [_vp]),
+    "fs_devkey_free": (None, [_vp]),
+    "fs_lwe_linear": (_int, [_vp, _vp, _sz, _sz, _u32, _vp, _vp, _vp, _vp]),
+    "fs_lwe_conv2d": (_int, [_vp, _vp, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32,
+                             _vp, _vp, _vp, _vp]),
+    "fs_lwe_add": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
+    "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
+    "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    "fs_ntt_polymul": (_int, [_vp, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfhesnn.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2309_09025_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != FS_OK:
+        raise FsError(fn, rc, lib().fs_last_error().decode())
+    return rc
+
+
+def _np_u32(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return a, a.ctypes.data_as(_u32p)
+
+
+def _np_i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_i32p)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ params
+
+def params_default(shape: int = 0) -> CParams:
+    p = CParams()
+    _check("fs_params_default", lib().fs_params_default(shape, ctypes.byref(p)))
+    return p
+
+
+# ------------------------------------------------------------------ client
+
+class Secret:
+    def __init__(self, handle, params: CParams):
+        self.h = ctypes.c_void_p(handle)
+        self.params = params
+
+    def __del__(self):
+        if _lib is not None and self.h:
+            _lib.fs_secret_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def export(self):
+        P = self.params
+        s = np.zeros(P.n, np.int32)
+        z = np.zeros(P.N, np.int32)
+        _check("fs_secret_export", lib().fs_secret_export(self.h, s.ctypes.data_as(_i32p),
+                                                          z.ctypes.data_as(_i32p)))
+        return s, z
+
+
+class EvalKey:
+    def __init__(self, handle, params: CParams):
+        self.h = ctypes.c_void_p(handle)
+        self.params = params
+
+    def __del__(self):
+        if _lib is not None and self.h:
+            _lib.fs_evk_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def export(self, bsk: bool = True, ksk: bool = True):
+        P = self.params
+        base = 1 << P.ks_base_bit
+        b = np.zeros((P.n, 2 * P.l, 2, P.N), np.uint32) if bsk else None
+        k = np.zeros((P.N, P.ks_t, base - 1, P.n + 1), np.uint32) if ksk else None
+        _check("fs_evk_export", lib().fs_evk_export(
+            self.h, b.ctypes.data_as(_u32p) if b is not None else None,
+            k.ctypes.data_as(_u32p) if k is not None else None))
+        return b, k
+
+
+def keygen(params: CParams, seed: int):
+    sk, evk = ctypes.c_void_p(), ctypes.c_void_p()
+    _check("fs_keygen", lib().fs_keygen(ctypes.byref(params), seed, ctypes.byref(sk),
+                                        ctypes.byref(evk)))
+    return Secret(sk.value, params), EvalKey(evk.value, params)
+
+
+def encrypt(sk: Secret, m, seed: int, first_index: int = 0) -> np.ndarray:
+    m, mp = _np_i32(np.atleast_1d(m))
+    ct = np.zeros((m.size, sk.params.n + 1), np.uint32)
+    _check("fs_encrypt", lib().fs_encrypt(sk.h, mp, m.size, seed, first_index,
+                                          ct.ctypes.data_as(_u32p)))
+    return ct
+
+
+def decrypt(sk: Secret, ct) -> np.ndarray:
+    ct, cp = _np_u32(np.atleast_2d(ct))
+    m = np.zeros(ct.shape[0], np.int32)
+    _check("fs_decrypt", lib().fs_decrypt(sk.h, cp, ct.shape[0], ct.shape[1],
+                                          m.ctypes.data_as(_i32p)))
+    return m
+
+
+def test_poly(N: int, p: int, f) -> np.ndarray:
+    f, fp = _np_i32(f)
+    v = np.zeros(N, np.uint32)
+    _check("fs_test_poly", lib().fs_test_poly(N, p, fp, v.ctypes.data_as(_u32p)))
+    return v
+
+
+def lif_luts(v_th: int, tau: int, p: int):
+    fire = np.zeros(p, np.int32)
+    reset = np.zeros(p, np.int32)
+    lif = CLif(v_th, tau)
+    _check("fs_lif_luts", lib().fs_lif_luts(ctypes.byref(lif), p, fire.ctypes.data_as(_i32p),
+                                            reset.ctypes.data_as(_i32p)))
+    return fire, reset
+
+
+def lif_range_check(v_th: int, tau: int, p: int, W, x_lo: int, x_hi: int):
+    """(M, holds) for the range condition of Theorem 4.1."""
+    W, wp = _np_i32(np.atleast_2d(W))
+    m = ctypes.c_int64()
+    rc = lib().fs_lif_range_check(ctypes.byref(CLif(v_th, tau)), p, wp, W.shape[0], W.shape[1],
+                                  x_lo, x_hi, ctypes.byref(m))
+    if rc not in (0, 1):
+        _check("fs_lif_range_check", rc)
+    return m.value, rc == 0
+
+
+# ------------------------------------------------------------------ server
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check("fs_ctx_create", lib().fs_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "h", None):
+            _lib.fs_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def reserve(self, N: int, max_jobs: int):
+        _check("fs_ctx_reserve", lib().fs_ctx_reserve(self.h, N, max_jobs))
+
+
+class DevKey:
+    def __init__(self, ctx: Context, evk: EvalKey):
+        h = ctypes.c_void_p()
+        _check("fs_evk_upload", lib().fs_evk_upload(ctx.h, evk.h, ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self.params = CParams()
+        _check("fs_devkey_params", lib().fs_devkey_params(h, ctypes.byref(self.params)))
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().fs_devkey_bytes(self.h))
+
+    def __del__(self):
+        if _lib is not None and getattr(self, "h", None):
+            _lib.fs_devkey_free(self.h)
+            self.h = ctypes.c_void_p()
+
+
+def evk_upload(ctx: Context, evk: EvalKey) -> DevKey:
+    return DevKey(ctx, evk)
+
+
+def lwe_linear(ctx: Context, W, x, y, add=None, stream=None):
+    O, I = W.shape
+    _check("fs_lwe_linear", lib().fs_lwe_linear(ctx.h, _dptr(W), O, I, x.shape[1], _dptr(x),
+                                                _dptr(add), _dptr(y), _stream(stream)))
+    return y
+
+
+def lwe_conv2d(ctx: Context, W, x, y, Ci, H, Wd, stride, pad, add=None, stream=None):
+    Co, _, K, _ = W.shape
+    _check("fs_lwe_conv2d", lib().fs_lwe_conv2d(ctx.h, _dptr(W), Ci, H, Wd, Co, K, stride, pad,
+                                                x.shape[-1], _dptr(x), _dptr(add), _dptr(y),
+                                                _stream(stream)))
+    return y
+
+
+def lwe_add(ctx: Context, a, b, y, stream=None):
+    _check("fs_lwe_add", lib().fs_lwe_add(ctx.h, _dptr(a), _dptr(b), a.numel(), _dptr(y),
+                                          _stream(stream)))
+    return y
+
+
+def pbs(ctx: Context, dk: DevKey, lut, x, out, keyswitch: bool = True, stream=None):
+    lut, lp = _np_i32(lut)
+    _check("fs_pbs", lib().fs_pbs(ctx.h, dk.h, lp, _dptr(x), x.shape[0], _dptr(out),
+                                  1 if keyswitch else 0, _stream(stream)))
+    return out
+
+
+def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out, stream=None):
+    lif = CLif(v_th, tau)
+    _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
+                                          _dptr(spike2_out), _dptr(v_out), _stream(stream)))
+
+
+def keyswitch(ctx: Context, dk: DevKey, x, out, stream=None):
+    _check("fs_keyswitch", lib().fs_keyswitch(ctx.h, dk.h, _dptr(x), x.shape[0], _dptr(out),
+                                              _stream(stream)))
+    return out
+
+
+def ntt_polymul(ctx: Context, N: int, dmax: int, d, b, out, stream=None):
+    R = d.shape[0]
+    _check("fs_ntt_polymul", lib().fs_ntt_polymul(ctx.h, N, R, dmax, _dptr(d), _dptr(b),
+                                                  _dptr(out), _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------ torch helpers
+
+def to_device(a: np.ndarray, device="cuda"):
+    """Host uint32/int32 array -> device int32 tensor holding the same bits."""
+    import torch
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """Device int32 tensor -> host uint32 array with the same bits."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def empty_ct(count: int, width: int, device="cuda"):
+    import torch
+    return torch.empty((count, width), dtype=torch.int32, device=device)

@@ -1,0 +1,113 @@
+"""Parity of the HIP path with the CPU oracle: every ciphertext word must be
+identical (integer work: bit-exact).  Inputs come from the shared seeded
+generators; each side encrypts and generates keys with its own code."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from paper_2309_09025_amd import fhesnn as F
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return F.to_device(a)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return F.to_host(t)
+
+
+@pytest.mark.parametrize("N,R,dmax", [(1024, 6, 64), (2048, 4, 512)])
+def test_ntt_polymul_matches_schoolbook(gpu_env, N, R, dmax):
+    ctx, _ = gpu_env
+    g = synth.rng(synth.SEED_DATA, 500 + N)
+    for case in ("random", "extreme"):
+        if case == "random":
+            d = g.integers(-dmax, dmax, size=(R, N)).astype(np.int32)
+            b = g.integers(0, 2 ** 32, size=(R, N), dtype=np.uint64).astype(np.uint32)
+        else:  # all products aligned at the largest magnitude
+            d = np.full((R, N), -dmax, np.int32)
+            b = np.full((R, N), 0x80000000, np.uint32)
+        out = torch.zeros(N, dtype=torch.int32, device="cuda")
+        F.ntt_polymul(ctx, N, dmax, _dev(d), _dev(b), out)
+        want = np.zeros(N, np.uint32)
+        for r in range(R):
+            want += O.negacyclic_mul(d[r].view(np.uint32), b[r])
+        assert np.array_equal(_host(out), want), case
+
+
+def _pbs_inputs(P, sk_lib, okeys, count, first=0):
+    m = synth.messages(synth.SEED_DATA, first + count, P.p)[first:]
+    ct_lib = F.encrypt(sk_lib, m, synth.SEED_ENC, first)
+    ct_or = O.encrypt(okeys.params, okeys.s, m, synth.SEED_ENC, first)
+    assert np.array_equal(ct_lib, ct_or)
+    return m, ct_or
+
+
+@pytest.mark.parametrize("keyswitch", [False, True])
+def test_pbs_fire_bit_exact(gpu_env, okeys_a, keyswitch):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m, ct = _pbs_inputs(P, sk, okeys_a, 24)
+    f = O.lut_fire(P.p, 4)
+    width = P.n + 1 if keyswitch else P.N + 1
+    out = torch.zeros((len(m), width), dtype=torch.int32, device="cuda")
+    F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=keyswitch)
+    got = _host(out)
+    want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct, keyswitch=keyswitch)
+    assert np.array_equal(got, want)
+
+
+def test_pbs_lif_bit_exact(gpu_env, okeys_a):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m, ct = _pbs_inputs(P, sk, okeys_a, 16, first=100)
+    s2 = torch.zeros((len(m), P.n + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    F.pbs_lif(ctx, dk, 4, 2, _dev(ct), s2, vv)
+    spikes, vnew = O.lif_step(okeys_a, 4, 2, ct)
+    assert np.array_equal(_host(s2), spikes)
+    assert np.array_equal(_host(vv), vnew)
+
+
+def test_keyswitch_bit_exact(gpu_env, okeys_a):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    x = synth.rng(synth.SEED_DATA, 600).integers(0, 2 ** 32, size=(5, P.N + 1),
+                                                  dtype=np.uint64).astype(np.uint32)
+    out = torch.zeros((5, P.n + 1), dtype=torch.int32, device="cuda")
+    F.keyswitch(ctx, dk, _dev(x), out)
+    assert np.array_equal(_host(out), O.keyswitch(okeys_a, x))
+
+
+@pytest.mark.parametrize("O_,I", [(1, 1), (32, 64), (37, 129), (256, 300)])
+def test_lwe_linear_bit_exact(gpu_env, O_, I):
+    ctx, _ = gpu_env
+    g = synth.rng(synth.SEED_DATA, 700 + I)
+    W = g.integers(-15, 16, size=(O_, I)).astype(np.int32)
+    x = g.integers(0, 2 ** 32, size=(I, 631), dtype=np.uint64).astype(np.uint32)
+    add = g.integers(0, 2 ** 32, size=(O_, 631), dtype=np.uint64).astype(np.uint32)
+    y = torch.zeros((O_, 631), dtype=torch.int32, device="cuda")
+    F.lwe_linear(ctx, _dev(W), _dev(x), y, add=_dev(add))
+    assert np.array_equal(_host(y), O.lwe_linear(W, x, add))
+    y2 = torch.zeros((O_, 631), dtype=torch.int32, device="cuda")
+    F.lwe_linear(ctx, _dev(W), _dev(x), y2)
+    assert np.array_equal(_host(y2), O.lwe_linear(W, x))
+
+
+@pytest.mark.parametrize("geom", [(1, 28, 28, 8, 5, 2, 2), (2, 7, 9, 3, 3, 1, 1), (3, 5, 5, 2, 5, 2, 0)])
+def test_lwe_conv2d_bit_exact(gpu_env, geom):
+    ctx, _ = gpu_env
+    Ci, H, Wd, Co, K, st, pd = geom
+    g = synth.rng(synth.SEED_DATA, 800 + H)
+    W = g.integers(-15, 16, size=(Co, Ci, K, K)).astype(np.int32)
+    x = g.integers(0, 2 ** 32, size=(Ci * H * Wd, 631), dtype=np.uint64).astype(np.uint32)
+    Ho = (H + 2 * pd - K) // st + 1
+    Wo = (Wd + 2 * pd - K) // st + 1
+    y = torch.zeros((Co * Ho * Wo, 631), dtype=torch.int32, device="cuda")
+    F.lwe_conv2d(ctx, _dev(W), _dev(x), y, Ci, H, Wd, st, pd)
+    assert np.array_equal(_host(y), O.lwe_conv2d(W, x, Ci, H, Wd, st, pd))

@@ -1,0 +1,91 @@
+"""Host-side checks of libfhesnn (no GPU): the C ABI loads and exports every
+symbol include/fhesnn.h declares; the client-side code (keygen, encrypt,
+decrypt, program functions) agrees byte for byte with the oracle, which is
+an independent implementation; argument errors come back as codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from paper_2309_09025_amd import fhesnn as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "fhesnn.h")).read()
+    names = re.findall(r"^FS_API\s+[\w\s\*]+?\b(fs_\w+)\s*\(", hdr, flags=re.M)
+    assert len(names) >= 25
+    L = ctypes.CDLL(F.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(F.SIGNATURES), set(names) ^ set(F.SIGNATURES)
+
+
+@pytest.mark.parametrize("shape,oparams", [(0, O.SHAPE_A), (1, O.SHAPE_B)])
+def test_keygen_matches_oracle(shape, oparams):
+    P = F.params_default(shape)
+    assert (P.n, P.N, P.l, P.bg_bit, P.p) == (oparams.n, oparams.N, oparams.l, oparams.bg_bit, oparams.p)
+    sk, evk = F.keygen(P, synth.SEED_KEYS)
+    K = O.keygen(oparams, synth.SEED_KEYS)
+    s, z = sk.export()
+    b, k = evk.export()
+    assert np.array_equal(s, K.s) and np.array_equal(z, K.z)
+    assert np.array_equal(b, K.bsk)
+    assert np.array_equal(k, K.ksk)
+
+
+def test_encrypt_decrypt_match_oracle(okeys_a):
+    P = F.params_default(0)
+    sk, _ = F.keygen(P, synth.SEED_KEYS)
+    m = synth.messages(synth.SEED_DATA, 500, P.p)
+    ct = F.encrypt(sk, m, synth.SEED_ENC, 17)
+    assert np.array_equal(ct, O.encrypt(O.SHAPE_A, okeys_a.s, m, synth.SEED_ENC, 17))
+    assert np.array_equal(F.decrypt(sk, ct), m)
+
+
+@pytest.mark.parametrize("p,V,tau", [(32, 4, 2), (32, 4, 0), (64, 9, 3), (32, 16, 2)])
+def test_program_functions_match_oracle(p, V, tau):
+    fire, reset = F.lif_luts(V, tau, p)
+    assert np.array_equal(fire, O.lut_fire(p, V))
+    assert np.array_equal(reset, O.lut_reset(p, V, tau))
+    for N in (1024, 2048):
+        assert np.array_equal(F.test_poly(N, p, fire), O.test_poly(N, p, fire))
+        assert np.array_equal(F.test_poly(N, p, reset), O.test_poly(N, p, reset))
+
+
+def test_errors_are_reported_not_raised_in_c():
+    bad = O.lut_reset(32, 4, 2).copy()
+    bad[17] = 15  # the printed fourth branch p/2 - leak: not negacyclic
+    with pytest.raises(F.FsError) as e:
+        F.test_poly(1024, 32, bad)
+    assert e.value.code == F.FS_EINVAL and "Theorem 2.1" in str(e.value)
+    P = F.params_default(0)
+    P.N = 512
+    with pytest.raises(F.FsError) as e:
+        F.keygen(P, 1)
+    assert e.value.code == F.FS_ENOTSUP
+    P = F.params_default(0)
+    P.version = 99
+    with pytest.raises(F.FsError):
+        F.keygen(P, 1)
+    with pytest.raises(F.FsError):
+        F.lif_luts(0, 2, 32)
+    with pytest.raises(F.FsError):
+        F.lif_luts(4, 1, 32)
+
+
+def test_range_check_theorem_4_1():
+    W = np.array([[1, -2, 3], [0, 1, 1]], np.int32)
+    M, ok = F.lif_range_check(4, 2, 32, W, 0, 2)  # max |I| = 6 * 2 = 12 -> M = 16 = p/2
+    assert M == 16 and ok
+    M, ok = F.lif_range_check(4, 2, 32, W, -3, 2)  # 6 * 3 = 18 -> M = 22 > 16
+    assert M == 22 and not ok
+    cfg = synth.TinyLIF()
+    x, Wt = cfg.data()
+    M, ok = F.lif_range_check(cfg.vth, cfg.tau, 32, Wt, 0, cfg.x_max)
+    assert not ok  # the tiny LIF workload wraps mod p (it is evaluated mod p)
