@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="bootstrappings the CPU oracle times (0: 2 per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="time every kernel variant again")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the bootstrappings of a batch "
@@ -84,6 +85,8 @@ def main():
     d_out = F.empty_ct(B, P.n + 1)
     ctx.reserve(P.N, B)
     stream = torch.cuda.current_stream()
+    from paper_2309_09025_amd import tune
+    variant, variant_ms = tune.tune_blind_rotation(ctx, dk, B, use_cache=not args.retune)
 
     def step(ev=None):
         if ev:
@@ -125,6 +128,7 @@ def main():
         "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
         "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
         "kernel_ms": round(br_avg, 4),
+        "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
     }
 
     cpu = None

@@ -153,6 +153,15 @@ FS_API int fs_ctx_destroy(fs_ctx* ctx);
  * stream capture into a graph). */
 FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
 
+/* Tuning of the blind-rotation kernel.  Every variant computes the same
+ * bits; they differ in when the key slice of a digit row is requested
+ * (before or after its forward transform) and in the register budget the
+ * compiler was held to (waves per SIMD).  fs_br_variants() returns the
+ * number of variants; fs_ctx_set_br_variant selects one for ring degree N
+ * on this context (default 0).  The autotuner times them and picks. */
+FS_API int fs_br_variants(void);
+FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
+
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
  * the exact negacyclic transform on the device; the KSK is copied as is.
  * Synchronous.  The device key is immutable afterwards and may be shared

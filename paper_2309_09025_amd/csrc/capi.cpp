@@ -26,6 +26,7 @@ struct fs_devkey {
   double* fwd_tw = nullptr;
   double* inv_tw = nullptr;
   double* post = nullptr;
+  fs::UniTw uni{};  // roots shared by all threads of a transform
   size_t bytes = 0;
 };
 
@@ -38,6 +39,8 @@ struct fs_ctx {
   std::map<std::vector<int32_t>, uint32_t*> tpoly;
   // NTT tables per ring degree for fs_ntt_polymul
   std::map<uint32_t, double*> tables;
+  // blind-rotation kernel variant per ring degree (chosen by the tuner)
+  std::map<uint32_t, int> br_variant;
 };
 
 namespace fs {
@@ -79,6 +82,7 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 int launch_rc(int rc, const char* what) {
   if (rc == 0) return FS_OK;
+  if (rc == -2) return fail(FS_EINVAL, std::string(what) + ": no such kernel variant");
   if (rc < 0) return fail(FS_ENOTSUP, std::string(what) + ": unsupported ring degree");
   return fail(FS_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)rc));
 }
@@ -125,9 +129,14 @@ void ntt_tables(uint32_t N, std::vector<double>& fwd, std::vector<double>& inv,
   for (uint32_t j = 0; j < N; ++j) post[j] = centred(mulm(powm(psi_inv, j), n_inv));
 }
 
-int upload_tables(uint32_t N, double** d_fwd, double** d_inv, double** d_post) {
+int upload_tables(uint32_t N, double** d_fwd, double** d_inv, double** d_post,
+                  UniTw* uni = nullptr) {
   std::vector<double> f, i, p;
   ntt_tables(N, f, i, p);
+  if (uni) {
+    for (int k = 0; k < 16; ++k) uni->fwd[k] = f[k];                 // psi^{brv(k)}
+    for (int m = 0; m < 8; ++m) uni->inv[m] = i[(size_t)m * N / 16];  // omega^{-m N/16}
+  }
   double* buf = nullptr;
   const size_t total = f.size() + i.size() + p.size();
   FS_HIP(hipMalloc(&buf, total * sizeof(double)));
@@ -204,8 +213,10 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
     ext = out0;
   }
   BrArgs br{in, tp[0], nlut == 2 ? tp[1] : tp[0], nlut, P.n, dk->bsk, dk->fwd_tw,
-            dk->inv_tw, dk->post, ext};
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, st), "blind rotation");
+            dk->inv_tw, dk->post, ext, dk->uni};
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, st), "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
   ks.in = ext;
@@ -375,6 +386,17 @@ int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs) {
   return ensure_ext(ctx, max_jobs * (size_t)(N + 1));
 }
 
+int fs_br_variants(void) { return blind_rotate_variants(); }
+
+int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  if (N != 1024 && N != 2048) return fail(FS_ENOTSUP, "ring degree without kernels");
+  if (variant < 0 || variant >= blind_rotate_variants()) return fail(FS_EINVAL, "no such kernel variant");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->br_variant[N] = variant;
+  return FS_OK;
+}
+
 int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   if (!ctx || !evk || !dk_out) return fail(FS_EINVAL, "fs_evk_upload: null argument");
   int rc = check_params(&evk->prm);
@@ -400,7 +422,7 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
   e = hipMalloc(&coef, bsk_words * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: staging allocation failed"));
-  rc = upload_tables(P.N, &dk->fwd_tw, &dk->inv_tw, &dk->post);
+  rc = upload_tables(P.N, &dk->fwd_tw, &dk->inv_tw, &dk->post, &dk->uni);
   if (rc) return cleanup(rc);
   e = hipMemcpy(coef, evk->bsk.data(), bsk_words * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)

@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "ntt_fp64.h"
+
 namespace fs {
 
 struct BrArgs {
@@ -18,6 +20,7 @@ struct BrArgs {
   const double* inv_tw;   // [N/2] omega^{-e}
   const double* post;     // [N] psi^{-j} N^{-1}
   uint32_t* ext;          // [jobs][N+1] extracted samples under z
+  UniTw uni;              // roots shared by all threads (scalar operands)
 };
 
 struct KsArgs {
@@ -31,7 +34,8 @@ struct KsArgs {
 
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
                       const double* tw, hipStream_t st);
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, hipStream_t st);
+int blind_rotate_variants();
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
                    const double* tw, const double* itw, const double* post, hipStream_t st);

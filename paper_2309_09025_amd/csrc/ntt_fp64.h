@@ -180,6 +180,229 @@ __device__ __forceinline__ void ntt_inv(double x[16], double* lds, const double*
   for (int r = 0; r < 16; ++r) x[r] = redc(mulmod(x[r], post[t + S::TP * r]));
 }
 
+// ---------------------------------------------------------------------------
+// Register-twiddle forms used by the blind rotation.  The same transforms as
+// ntt_fwd / ntt_inv, but every root comes from registers instead of a table
+// load inside the loop:
+//  - forward round A and inverse round C' use roots that are the same for
+//    all threads (they depend on register bits only); they are passed in the
+//    kernel-argument segment and read as scalars;
+//  - in the other rounds, stage s with register bits at LO has a root that
+//    depends on the thread and on r >> (b+1) (forward) or r & (2^b - 1)
+//    (inverse), b = s - LO: 16 >> (b+1) resp. 2^b values per thread, loaded
+//    once per use site into a small register array.
+
+// forward: number of per-thread roots of stages SHI..SLO, and the offset of
+// stage S inside that block
+template <int LO, int SHI, int SLO>
+__host__ __device__ constexpr int fwd_lane_count() {
+  int c = 0;
+  for (int s = SHI; s >= SLO; --s) c += 16 >> (s - LO + 1);
+  return c;
+}
+__host__ __device__ constexpr int fwd_lane_off(int LO, int SHI, int S) {
+  int c = 0;
+  for (int s = SHI; s > S; --s) c += 16 >> (s - LO + 1);
+  return c;
+}
+// inverse: 2^b roots per stage
+template <int LO, int SLO, int SHI>
+__host__ __device__ constexpr int inv_lane_count() {
+  int c = 0;
+  for (int s = SLO; s <= SHI; ++s) c += 1 << (s - LO);
+  return c;
+}
+__host__ __device__ constexpr int inv_lane_off(int LO, int SLO, int S) {
+  int c = 0;
+  for (int s = SLO; s < S; ++s) c += 1 << (s - LO);
+  return c;
+}
+
+template <int LOGN>
+struct RegTw {
+  using S = NttShape<LOGN>;
+  // forward rounds B (stages LOGN-5..4, LO = LOB) and C (stages 3..0, LO = 0)
+  static constexpr int FB = fwd_lane_count<S::LOB, LOGN - 5, 4>();
+  static constexpr int FC = fwd_lane_count<0, 3, 0>();
+  static constexpr int FWD = FB + FC;
+  // inverse rounds B' (stages 4..LOGN-5) and A' (LOGN-4..LOGN-1), plus the twist
+  static constexpr int IB = inv_lane_count<S::LOB, 4, LOGN - 5>();
+  static constexpr int IA = inv_lane_count<S::LOA, LOGN - 4, LOGN - 1>();
+  static constexpr int INV = IB + IA + 16;
+};
+
+// Uniform roots: forward round A uses psi^{brv(k)}, k = 1..15; inverse round
+// C' uses omega^{-m N/16}, m = 0..7.
+struct UniTw {
+  double fwd[16];
+  double inv[8];
+};
+
+template <int LOGN, int LO, int SHI, int SLO>
+__device__ __forceinline__ void load_fwd_lane(double* w, const double* __restrict__ tw, int t) {
+  constexpr int N = 1 << LOGN;
+#pragma unroll
+  for (int s = SHI; s >= SLO; --s) {
+    const int b = s - LO;
+#pragma unroll
+    for (int q = 0; q < (16 >> (b + 1)); ++q) {
+      const int j = jmap<LOGN, LO>(t, q << (b + 1));
+      w[fwd_lane_off(LO, SHI, s) + q] =
+          tw[(N >> (s + 1)) + (j >> (s + 1))];
+    }
+  }
+}
+
+template <int LOGN, int LO, int SHI, int SLO>
+__device__ __forceinline__ void fwd_stages_reg(double x[16], const double* w) {
+#pragma unroll
+  for (int s = SHI; s >= SLO; --s) {
+    const int b = s - LO;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r & (1 << b)) continue;
+      const int r2 = r | (1 << b);
+      const double m = mulmod(x[r2], w[fwd_lane_off(LO, SHI, s) + (r >> (b + 1))]);
+      x[r2] = x[r] - m;
+      x[r] = x[r] + m;
+    }
+  }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
+  using S = NttShape<LOGN>;
+#pragma unroll
+  for (int s = LOGN - 1; s >= LOGN - 4; --s) {
+    const int b = s - S::LOA;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r & (1 << b)) continue;
+      const int r2 = r | (1 << b);
+      // k = N/2^{s+1} + j/2^{s+1} with j = t + TP r: the thread part drops out
+      const double m = mulmod(x[r2], u.fwd[(1 << (LOGN - 1 - s)) + (r >> (b + 1))]);
+      x[r2] = x[r] - m;
+      x[r] = x[r] + m;
+    }
+  }
+}
+
+// Forward transform with register roots (same result as ntt_fwd).  The
+// per-thread roots of rounds B and C are requested one round ahead.
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
+                                            const double* __restrict__ tw, int t) {
+  using S = NttShape<LOGN>;
+  using R = RegTw<LOGN>;
+  double wb[R::FB];
+  load_fwd_lane<LOGN, S::LOB, LOGN - 5, 4>(wb, tw, t);
+  fwd_roundA_uni<LOGN>(x, u);
+  reduce16<S::N>(x);
+  exchange<LOGN, S::LOA, S::LOB>(x, lds, t);
+  double wc[R::FC];
+  load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);
+  fwd_stages_reg<LOGN, S::LOB, LOGN - 5, 4>(x, wb);
+  reduce16<S::N>(x);
+  exchange<LOGN, S::LOB, 0>(x, lds, t);
+  fwd_stages_reg<LOGN, 0, 3, 0>(x, wc);
+  reduce16<S::N>(x);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void load_fwd_tw(double* wf, const double* __restrict__ tw, int t) {
+  using S = NttShape<LOGN>;
+  load_fwd_lane<LOGN, S::LOB, LOGN - 5, 4>(wf, tw, t);
+  load_fwd_lane<LOGN, 0, 3, 0>(wf + RegTw<LOGN>::FB, tw, t);
+}
+
+template <int LOGN, int LO, int SLO, int SHI>
+__device__ __forceinline__ void load_inv_lane(double* w, const double* __restrict__ itw, int t) {
+  constexpr int N = 1 << LOGN;
+#pragma unroll
+  for (int s = SLO; s <= SHI; ++s) {
+    const int b = s - LO;
+#pragma unroll
+    for (int q = 0; q < (1 << b); ++q) {
+      const int i = jmap<LOGN, LO>(t, q);
+      w[inv_lane_off(LO, SLO, s) + q] = itw[(i & ((1 << s) - 1)) * (N >> (s + 1))];
+    }
+  }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void load_inv_tw(double* wi, const double* __restrict__ itw,
+                                            const double* __restrict__ post, int t) {
+  using S = NttShape<LOGN>;
+  using R = RegTw<LOGN>;
+  load_inv_lane<LOGN, S::LOB, 4, LOGN - 5>(wi, itw, t);
+  load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wi + R::IB, itw, t);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) wi[R::IB + R::IA + r] = post[t + S::TP * r];
+}
+
+template <int LOGN, int LO, int SLO, int SHI>
+__device__ __forceinline__ void inv_stages_reg(double x[16], const double* w) {
+#pragma unroll
+  for (int s = SLO; s <= SHI; ++s) {
+    const int b = s - LO;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r & (1 << b)) continue;
+      const int r2 = r | (1 << b);
+      const double m = mulmod(x[r2], w[inv_lane_off(LO, SLO, s) + (r & ((1 << b) - 1))]);
+      x[r2] = x[r] - m;
+      x[r] = x[r] + m;
+    }
+  }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void inv_roundC_uni(double x[16], const UniTw& u, int slo, int shi) {
+#pragma unroll
+  for (int s = 0; s <= 3; ++s) {
+    if (s < slo || s > shi) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r & (1 << s)) continue;
+      const int r2 = r | (1 << s);
+      const int m8 = (r & ((1 << s) - 1)) << (3 - s);  // e = m8 * N / 16
+      const double m = m8 == 0 ? x[r2] : mulmod(x[r2], u.inv[m8]);
+      x[r2] = x[r] - m;
+      x[r] = x[r] + m;
+    }
+  }
+}
+
+// Inverse transform with register roots (same result as ntt_inv).  The
+// per-thread roots of each round are requested one round ahead, so their
+// latency overlaps the previous round.
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const UniTw& u,
+                                            const double* __restrict__ itw,
+                                            const double* __restrict__ post, int t) {
+  using S = NttShape<LOGN>;
+  using R = RegTw<LOGN>;
+  double wb[R::IB];
+  load_inv_lane<LOGN, S::LOB, 4, LOGN - 5>(wb, itw, t);
+  reduce16<S::N>(x);
+  inv_roundC_uni<LOGN>(x, u, 0, 1);  // < 2.1 P
+  reduce16<S::N>(x);
+  inv_roundC_uni<LOGN>(x, u, 2, 3);  // < 2.3 P
+  reduce16<S::N>(x);
+  exchange<LOGN, 0, S::LOB>(x, lds, t);
+  double wa[R::IA];
+  load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wa, itw, t);
+  inv_stages_reg<LOGN, S::LOB, 4, LOGN - 5>(x, wb);  // < 3.1 P
+  reduce16<S::N>(x);
+  exchange<LOGN, S::LOB, S::LOA>(x, lds, t);
+  double wp[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) wp[r] = post[t + S::TP * r];
+  inv_stages_reg<LOGN, S::LOA, LOGN - 4, LOGN - 1>(x, wa);  // < 4.4 P
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = redc(mulmod(x[r], wp[r]));
+}
+
 // Low 32 bits of an integer-valued double of magnitude < 2^52.
 __device__ __forceinline__ uint32_t low32(double e) {
   const double hi = __builtin_floor(e * 0x1p-32);

@@ -58,13 +58,20 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 //   inverse NTT of the two accumulators -> exact integers -> ACC_c +=
 // Initialization ACC = (0, X^{-b~} v) and sample extraction of
 // coefficient 0 are fused at both ends.
-template <int LOGN, int L, int BG, int LIMBS>
-__global__ void __launch_bounds__(NttShape<LOGN>::TP)
+//
+// Latency: the key slice of a digit row is requested before that row's
+// forward transform and consumed after it; the roots shared by all threads
+// come from the kernel-argument segment and the per-thread ones are loaded
+// once per step (forward) or per inverse phase, never inside a transform.
+template <int LOGN, int L, int BG, int LIMBS, bool PREF, int WPE>
+__global__ void __launch_bounds__(NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
+  using R = RegTw<LOGN>;
   constexpr int N = S::N, TP = S::TP, ROWS = 2 * L;
-  constexpr uint32_t HALF = 1u << (BG - 1), MASK = (1u << BG) - 1;
+  constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr uint32_t NU = LOGN + 1;  // log2(2N)
+  constexpr int G = 2 * LIMBS;       // key values per slot and digit row
   __shared__ double lds[S::LDS_DOUBLES];
   __shared__ uint32_t acc[2][N];
 
@@ -108,7 +115,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) { p0[lb][r] = 0.0; p1[lb][r] = 0.0; }
 
-    const double* bsk_i = bsk + (size_t)i * ROWS * 16 * TP * 2 * LIMBS;
+    const double* bsk_i = bsk + (size_t)i * ROWS * 16 * TP * G;
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
       uint32_t d[16];
@@ -124,21 +131,35 @@ blind_rotate_kernel(BrArgs a) {
       }
 #pragma unroll 1
       for (int lv = 0; lv < L; ++lv) {
+        // request this digit row's key slice before the transform (PREF) or
+        // after it (fewer live registers)
+        const double* row = bsk_i + (size_t)(c * L + lv) * 16 * TP * G;
+        double g[16][G];
+        if (PREF) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+#pragma unroll
+            for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
+        }
+        const uint32_t sh = 32 - (lv + 1) * BG;
         double x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          x[r] = (double)((int32_t)((d[r] >> (32 - (lv + 1) * BG)) & MASK) - (int32_t)HALF);
-        ntt_fwd<LOGN>(x, lds, a.fwd_tw, t);
-        const double* row = bsk_i + (size_t)(c * L + lv) * 16 * TP * 2 * LIMBS;
+          x[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+        ntt_fwd_reg<LOGN>(x, lds, a.uni, a.fwd_tw, t);
+        if (!PREF) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const double* g = row + ((size_t)r * TP + t) * 2 * LIMBS;
+          for (int r = 0; r < 16; ++r)
+#pragma unroll
+            for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
 #pragma unroll
           for (int lb = 0; lb < LIMBS; ++lb) {
-            p0[lb][r] += mulmod(x[r], g[lb]);
-            p1[lb][r] += mulmod(x[r], g[LIMBS + lb]);
+            p0[lb][r] += mulmod(x[r], g[r][lb]);
+            p1[lb][r] += mulmod(x[r], g[r][LIMBS + lb]);
           }
-        }
       }
     }
     // inverse transforms; p* hold sums of 2L products, each < 0.65 P
@@ -148,7 +169,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int lb = 0; lb < LIMBS; ++lb) {
         double* y = c == 0 ? p0[lb] : p1[lb];
-        ntt_inv<LOGN>(y, lds, a.inv_tw, a.post, t);
+        ntt_inv_reg<LOGN>(y, lds, a.uni, a.inv_tw, a.post, t);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t part = low32(y[r]);
@@ -280,12 +301,29 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
   return 0;
 }
 
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, hipStream_t st) {
+// Kernel variants the tuner chooses from: (key-slice prefetch, minimum waves
+// per SIMD the register allocation must allow).
+int blind_rotate_variants() { return 4; }
+
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st) {
   if (jobs == 0) return 0;
+  const dim3 g((uint32_t)jobs);
   if (N == 1024) {
-    blind_rotate_kernel<10, 3, 7, 1><<<dim3((uint32_t)jobs), 64, 0, st>>>(a);
+    switch (variant) {
+      case 0: blind_rotate_kernel<10, 3, 7, 1, false, 2><<<g, 64, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<10, 3, 7, 1, true, 1><<<g, 64, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<10, 3, 7, 1, true, 2><<<g, 64, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<10, 3, 7, 1, false, 1><<<g, 64, 0, st>>>(a); break;
+      default: return -2;
+    }
   } else if (N == 2048) {
-    blind_rotate_kernel<11, 2, 10, 2><<<dim3((uint32_t)jobs), 128, 0, st>>>(a);
+    switch (variant) {
+      case 0: blind_rotate_kernel<11, 2, 10, 2, false, 1><<<g, 128, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<11, 2, 10, 2, true, 1><<<g, 128, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<11, 2, 10, 2, true, 2><<<g, 128, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<11, 2, 10, 2, false, 2><<<g, 128, 0, st>>>(a); break;
+      default: return -2;
+    }
   } else {
     return -1;
   }

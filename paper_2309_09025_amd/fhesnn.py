@@ -72,6 +72,8 @@ SIGNATURES = {
     "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
     "fs_ctx_destroy": (_int, [_vp]),
     "fs_ctx_reserve": (_int, [_vp, _u32, _sz]),
+    "fs_br_variants": (_int, []),
+    "fs_ctx_set_br_variant": (_int, [_vp, _u32, _int]),
     "fs_evk_upload": (_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     "fs_devkey_params": (_int, [_vp, _PP]),
     "fs_devkey_bytes": (_sz, [_vp]),
@@ -252,6 +254,13 @@ class Context:
 
     def reserve(self, N: int, max_jobs: int):
         _check("fs_ctx_reserve", lib().fs_ctx_reserve(self.h, N, max_jobs))
+
+    def set_br_variant(self, N: int, variant: int):
+        _check("fs_ctx_set_br_variant", lib().fs_ctx_set_br_variant(self.h, N, variant))
+
+
+def br_variants() -> int:
+    return int(lib().fs_br_variants())
 
 
 class DevKey:

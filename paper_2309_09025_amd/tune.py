@@ -1,0 +1,89 @@
+"""Autotuner for the blind-rotation kernel.
+
+Every kernel variant computes the same bits; the tuner times each one on a
+batch of the caller's shape (bootstrapping runtime does not depend on the
+ciphertext contents, apart from the rare skipped step a~_i = 0, so uniform
+random samples are representative) and keeps the fastest.  Results are
+cached in tune_cache.json next to this file, keyed by
+(GPU architecture, N, l, Bg, batch bucket).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from . import fhesnn as F
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def _bucket(jobs: int) -> int:
+    """Batch sizes are tuned per power-of-two bucket."""
+    b = 1
+    while b < jobs:
+        b *= 2
+    return b
+
+
+def _key(arch: str, P, jobs: int) -> str:
+    return f"{arch}|N={P.N}|l={P.l}|bg={P.bg_bit}|jobs={_bucket(jobs)}"
+
+
+def _load():
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def arch_name() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
+                        use_cache: bool = True, store: bool = True):
+    """Pick the fastest blind-rotation variant for `jobs` bootstrappings per
+    launch; sets it on ctx and returns (variant, {variant: ms})."""
+    import torch
+    P = dk.params
+    key = _key(arch_name(), P, jobs)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        best = int(cache[key]["variant"])
+        ctx.set_br_variant(P.N, best)
+        return best, {int(k): v for k, v in cache[key]["ms"].items()}
+    g = np.random.Generator(np.random.PCG64(1234))
+    x = F.to_device(g.integers(0, 2 ** 32, size=(jobs, P.n + 1), dtype=np.uint64).astype(np.uint32))
+    ext = F.empty_ct(jobs, P.N + 1)
+    lut = np.where(np.arange(P.p) < P.p // 2, 1, -1).astype(np.int32)
+    stream = torch.cuda.current_stream()
+    times = {}
+    for v in range(F.br_variants()):
+        ctx.set_br_variant(P.N, v)
+        F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)  # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times[v] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    ctx.set_br_variant(P.N, best)
+    if store:
+        cache = _load()
+        cache[key] = {"variant": best, "ms": {str(k): round(t, 4) for k, t in times.items()}}
+        _store(cache)
+    return best, times
