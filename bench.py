@@ -46,6 +46,27 @@ def alg_ops_per_pbs(n, N, l):
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+def _traffic(shape, batch):
+    """HBM bytes per blind-rotation launch from the committed counter runs, or
+    None when the kernel sources changed since they were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(path) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256()
+        for p in rec["sources"]:
+            with open(os.path.join(ROOT, p), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != rec["source_sha"]:
+            continue
+        for name, v in rec.items():
+            if name.startswith("blind_rotate_kernel") and isinstance(v, dict) \
+                    and v.get("batch") == batch and shape == 0:
+                return v["hbm_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +78,8 @@ def main():
                     help="bootstrappings the CPU oracle times (0: 2 per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="time every kernel variant again")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the bootstrappings of a batch "
@@ -83,15 +106,18 @@ def main():
     d_in = F.to_device(ct)
     d_ext = F.empty_ct(B, P.N + 1)
     d_out = F.empty_ct(B, P.n + 1)
+    d_ks = F.empty_ct(B, P.n + 1)
     ctx.reserve(P.N, B)
     stream = torch.cuda.current_stream()
     from paper_2309_09025_amd import tune
     variant, variant_ms = tune.tune_blind_rotation(ctx, dk, B, use_cache=not args.retune)
 
     def step(ev=None):
+        # blind rotation + sample extraction, then the batched key switch:
+        # the two kernels fs_pbs(keyswitch=1) launches for a batch this size
         if ev:
             ev[0].record(stream)
-        F.pbs(ctx, dk, fire, d_in, d_ext, keyswitch=False, stream=stream)  # BR + extract
+        F.pbs(ctx, dk, fire, d_in, d_ext, keyswitch=False, stream=stream)
         if ev:
             ev[1].record(stream)
         F.keyswitch(ctx, dk, d_ext, d_out, stream=stream)
@@ -113,6 +139,16 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     pbs_per_s = B / (ms_per_step / 1e3)
 
+    # the library's own entry point on the same batch gives the same bits
+    F.pbs(ctx, dk, fire, d_in, d_ks, keyswitch=True, stream=stream)
+    torch.cuda.synchronize()
+    if args.copy_mib:
+        # plain device copy of known size, for calibrating HBM byte counters
+        src = torch.empty(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     out = F.to_host(d_out)
     dec = F.decrypt(sk, out)
     want = np.where(((m.astype(np.int64) - 4) % P.p) < P.p // 2, 1, -1)
@@ -125,7 +161,7 @@ def main():
         "bound": "alu", "kernel": "blind_rotate_kernel",
         "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
         "unit": "TOP/s (binary64 VALU lane-instructions)",
-        "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
+        "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": _traffic(shape, B),
         "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
         "kernel_ms": round(br_avg, 4),
         "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
@@ -159,8 +195,9 @@ def main():
                                f"messages uniform in Z_{P.p}, LIF threshold test polynomial, "
                                f"N={P.N} k=1 l={P.l} Bg=2^{P.bg_bit}, KS base 2^{P.ks_base_bit} t={P.ks_t}",
                    "batch": B, "n": P.n, "N": P.N, "l": P.l, "bg_bit": P.bg_bit, "p": P.p},
-        "breakdown_ms": {"blind_rotate+extract": round(br_avg, 4),
-                         "keyswitch": round(sum(ks_ms) / len(ks_ms), 4)},
+        "breakdown_ms": {"blind_rotate_kernel": round(br_avg, 4),
+                         "keyswitch_batched_kernel": round(sum(ks_ms) / len(ks_ms), 4)},
+        "fs_pbs_matches_step": bool(np.array_equal(F.to_host(d_ks), out)),
         "decrypt_ok_fraction": decrypt_ok,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -41,6 +41,9 @@ struct fs_ctx {
   std::map<uint32_t, double*> tables;
   // blind-rotation kernel variant per ring degree (chosen by the tuner)
   std::map<uint32_t, int> br_variant;
+  // batches up to this many bootstrappings key-switch inside the blind
+  // rotation kernel; larger ones use the batched key-switch kernel
+  size_t fuse_max_jobs = 64;
 };
 
 namespace fs {
@@ -204,22 +207,44 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
             const uint32_t plain_add[2], int keyswitch, hipStream_t st) {
   const fs_params& P = dk->prm;
   const size_t jobs = B * nlut;
-  uint32_t* ext = nullptr;
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  BrArgs br{};
+  br.in = in;
+  br.tpoly0 = tp[0];
+  br.tpoly1 = nlut == 2 ? tp[1] : tp[0];
+  br.nlut = nlut;
+  br.n = P.n;
+  br.bsk = dk->bsk;
+  br.fwd_tw = dk->fwd_tw;
+  br.inv_tw = dk->inv_tw;
+  br.post = dk->post;
+  br.uni = dk->uni;
+  // key switching fused into the blind-rotation epilogue for the built-in
+  // digit shape (t = 8, base 4, n + 1 <= 1024)
+  // (one launch; best for small batches, where the rows a sample reads
+  // are not shared with other samples anyway)
+  const bool fuse = keyswitch && jobs <= ctx->fuse_max_jobs && P.ks_t == 8 &&
+                    P.ks_base_bit == 2 && P.n + 1 <= 1024;
+  if (fuse) {
+    br.ksk = dk->ksk;
+    br.out0 = out0;
+    br.out1 = out1;
+    br.plain_add[0] = plain_add[0];
+    br.plain_add[1] = plain_add[1];
+    return launch_rc(launch_blind_rotate(P.N, br, jobs, variant, true, st), "blind rotation");
+  }
   if (keyswitch) {
     int rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
     if (rc) return rc;
-    ext = ctx->ext;
+    br.ext = ctx->ext;
   } else {
-    ext = out0;
+    br.ext = out0;
   }
-  BrArgs br{in, tp[0], nlut == 2 ? tp[1] : tp[0], nlut, P.n, dk->bsk, dk->fwd_tw,
-            dk->inv_tw, dk->post, ext, dk->uni};
-  auto vit = ctx->br_variant.find(P.N);
-  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, st), "blind rotation");
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, false, st), "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
-  ks.in = ext;
+  ks.in = br.ext;
   ks.ksk = dk->ksk;
   ks.out0 = out0;
   ks.out1 = out1;
@@ -418,7 +443,8 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   const size_t bsk_ntt = bsk_words * limbs;  // doubles
   hipError_t e = hipMalloc(&dk->bsk, bsk_ntt * sizeof(double));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: BSK allocation failed"));
-  e = hipMalloc(&dk->ksk, evk->ksk.size() * sizeof(uint32_t));
+  // the KSK is followed by one all-zero row (digit value 0 in the fused key switch)
+  e = hipMalloc(&dk->ksk, (evk->ksk.size() + P.n + 1) * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
   e = hipMalloc(&coef, bsk_words * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: staging allocation failed"));
@@ -428,6 +454,8 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   if (e == hipSuccess)
     e = hipMemcpy(dk->ksk, evk->ksk.data(), evk->ksk.size() * sizeof(uint32_t),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemset(dk->ksk + evk->ksk.size(), 0, (P.n + 1) * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: copy"));
   rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
                  "BSK conversion");

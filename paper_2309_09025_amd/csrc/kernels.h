@@ -19,8 +19,13 @@ struct BrArgs {
   const double* fwd_tw;   // [N] psi^{brv(k)}
   const double* inv_tw;   // [N/2] omega^{-e}
   const double* post;     // [N] psi^{-j} N^{-1}
-  uint32_t* ext;          // [jobs][N+1] extracted samples under z
+  uint32_t* ext;          // [jobs][N+1] extracted samples under z (not fused)
   UniTw uni;              // roots shared by all threads (scalar operands)
+  // fused sample extraction + key switch (t = 8 digits of base 4):
+  const uint32_t* ksk;    // [N][8][3][n+1] followed by one all-zero row
+  uint32_t* out0;         // program function 0 outputs, [jobs/nlut][n+1]
+  uint32_t* out1;         // program function 1 outputs (nlut == 2)
+  uint32_t plain_add[2];  // Delta * c added to b per program function
 };
 
 struct KsArgs {
@@ -35,7 +40,8 @@ struct KsArgs {
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
                       const double* tw, hipStream_t st);
 int blind_rotate_variants();
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st);
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool fused_ks,
+                        hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
                    const double* tw, const double* itw, const double* post, hipStream_t st);

@@ -63,7 +63,7 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // forward transform and consumed after it; the roots shared by all threads
 // come from the kernel-argument segment and the per-thread ones are loaded
 // once per step (forward) or per inverse phase, never inside a transform.
-template <int LOGN, int L, int BG, int LIMBS, bool PREF, int WPE>
+template <int LOGN, int L, int BG, int LIMBS, bool PREF, int WPE, bool KS>
 __global__ void __launch_bounds__(NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
@@ -182,14 +182,54 @@ blind_rotate_kernel(BrArgs a) {
     __syncthreads();
   }
 
-  // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
-  uint32_t* out = a.ext + job * (size_t)(N + 1);
+  if constexpr (!KS) {
+    // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
+    uint32_t* out = a.ext + job * (size_t)(N + 1);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int j = t + TP * r;
-    out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
+    for (int r = 0; r < 16; ++r) {
+      const int j = t + TP * r;
+      out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
+    }
+    if (t == 0) out[N] = acc[1][0];
+  } else {
+    // Fused Sample Extraction + Key Switching z -> s.  The extracted mask is
+    // a'_0 = ACC_a[0], a'_i = -ACC_a[N-i]; each a'_i is rounded to 16 bits
+    // and split into eight base-4 digits (most significant first); digit d
+    // of coefficient i at position j selects KSK[i][j][d-1], d = 0 the
+    // all-zero row.  The digits are the same for every thread (scalar);
+    // thread t accumulates output words t, t + TP, ... .
+    constexpr int KT = 8, KB = 2, PREC = KT * KB;
+    constexpr int WPT = 1024 / TP;  // words per thread, n + 1 <= 1024
+    const uint32_t w1 = n + 1;
+    uint32_t o[WPT];
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) o[k] = 0u;
+    const uint32_t* __restrict__ ksk = a.ksk;
+    const uint32_t* zero = ksk + (size_t)N * KT * 3 * w1;
+    for (int i = 0; i < N; ++i) {
+      const uint32_t ai = __builtin_amdgcn_readfirstlane(i == 0 ? acc[0][0] : 0u - acc[0][N - i]);
+      const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
+      const uint32_t* rowi = ksk + (size_t)i * KT * 3 * w1;
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        const uint32_t d = (abar >> ((KT - 1 - j) * KB)) & 3u;
+        const uint32_t* row = d ? rowi + (size_t)(j * 3 + d - 1) * w1 : zero;
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+          const uint32_t w = t + TP * k;
+          if (w < w1) o[k] -= row[w];
+        }
+      }
+    }
+    const uint32_t lut = (uint32_t)(job % a.nlut);
+    uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (job / a.nlut) * (size_t)w1;
+    const uint32_t bprime = acc[1][0] + a.plain_add[lut];
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const uint32_t w = t + TP * k;
+      if (w < w1) out[w] = o[k] + (w == n ? bprime : 0u);
+    }
   }
-  if (t == 0) out[N] = acc[1][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -222,6 +262,75 @@ keyswitch_kernel(KsArgs a) {
   }
   uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * stride;
   out[w] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched key switching (t = 8 digits of base 4).  A block serves KC = 16
+// samples and a 256-word slice of the output: every KSK row word a thread
+// loads is used by all 16 samples.  Digits of all 16 samples for position
+// (i, j) are packed two bits each into one word in LDS; per (i, j) a thread
+// loads the three candidate rows and each sample subtracts the one its
+// digit selects (the digit is the same for every thread, so the selection
+// costs no divergence).  Output routing and the +Delta epilogue are those of
+// keyswitch_kernel.
+constexpr int KC = 16;
+
+template <int N>
+__global__ void __launch_bounds__(256)
+keyswitch_batched_kernel(KsArgs a, uint32_t count) {
+  constexpr int KT = 8, KB = 2, PREC = KT * KB;
+  __shared__ uint32_t dig[N * KT];
+  const uint32_t tid = threadIdx.x;
+  const size_t m0 = (size_t)blockIdx.x * KC;
+  const uint32_t n = a.n, w1 = n + 1;
+  // digits of the KC samples, packed: bits 2c..2c+1 of dig[i*8 + j]
+  for (uint32_t i = tid; i < (uint32_t)N; i += 256) {
+    uint32_t words[KT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) words[j] = 0u;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      if (m0 + c < count) {
+        const uint32_t ai = a.in[(m0 + c) * (size_t)(N + 1) + i];
+        const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
+#pragma unroll
+        for (int j = 0; j < KT; ++j) words[j] |= ((abar >> ((KT - 1 - j) * KB)) & 3u) << (2 * c);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KT; ++j) dig[i * KT + j] = words[j];
+  }
+  __syncthreads();
+  const uint32_t w = blockIdx.y * 256 + tid;
+  const uint32_t wc = w < w1 ? w : n;  // clamp the idle tail threads in bounds
+  uint32_t acc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) acc[c] = 0u;
+  const uint32_t* __restrict__ ksk = a.ksk + wc;
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+      const uint32_t dw = __builtin_amdgcn_readfirstlane(dig[i * KT + j]);
+      const uint32_t* rows = ksk + (size_t)((i * KT + j) * 3) * w1;
+      const uint32_t r1 = rows[0], r2 = rows[w1], r3 = rows[2 * w1];
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const uint32_t d = (dw >> (2 * c)) & 3u;
+        if (d) acc[c] -= d == 1 ? r1 : (d == 2 ? r2 : r3);
+      }
+    }
+  }
+  if (w >= w1) return;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const size_t m = m0 + c;
+    if (m >= count) break;
+    const uint32_t lut = (uint32_t)(m % a.nlut);
+    const uint32_t* in = a.in + m * (size_t)(N + 1);
+    const uint32_t v = w == n ? acc[c] + in[N] + a.plain_add[lut] : acc[c];
+    uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * (size_t)w1;
+    out[w] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -305,23 +414,23 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // per SIMD the register allocation must allow).
 int blind_rotate_variants() { return 4; }
 
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st) {
-  if (jobs == 0) return 0;
+template <bool KS>
+static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st) {
   const dim3 g((uint32_t)jobs);
   if (N == 1024) {
     switch (variant) {
-      case 0: blind_rotate_kernel<10, 3, 7, 1, false, 2><<<g, 64, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<10, 3, 7, 1, true, 1><<<g, 64, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<10, 3, 7, 1, true, 2><<<g, 64, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<10, 3, 7, 1, false, 1><<<g, 64, 0, st>>>(a); break;
+      case 0: blind_rotate_kernel<10, 3, 7, 1, false, 2, KS><<<g, 64, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<10, 3, 7, 1, true, 1, KS><<<g, 64, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<10, 3, 7, 1, true, 2, KS><<<g, 64, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<10, 3, 7, 1, false, 1, KS><<<g, 64, 0, st>>>(a); break;
       default: return -2;
     }
   } else if (N == 2048) {
     switch (variant) {
-      case 0: blind_rotate_kernel<11, 2, 10, 2, false, 1><<<g, 128, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<11, 2, 10, 2, true, 1><<<g, 128, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<11, 2, 10, 2, true, 2><<<g, 128, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<11, 2, 10, 2, false, 2><<<g, 128, 0, st>>>(a); break;
+      case 0: blind_rotate_kernel<11, 2, 10, 2, false, 1, KS><<<g, 128, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<11, 2, 10, 2, true, 1, KS><<<g, 128, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<11, 2, 10, 2, true, 2, KS><<<g, 128, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<11, 2, 10, 2, false, 2, KS><<<g, 128, 0, st>>>(a); break;
       default: return -2;
     }
   } else {
@@ -331,10 +440,24 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, h
   return 0;
 }
 
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool fused_ks,
+                        hipStream_t st) {
+  if (jobs == 0) return 0;
+  return fused_ks ? launch_br<true>(N, a, jobs, variant, st)
+                  : launch_br<false>(N, a, jobs, variant, st);
+}
+
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {
   if (count == 0) return 0;
-  dim3 g((uint32_t)count, (a.n + 1 + 255) / 256);
-  keyswitch_kernel<<<g, 256, 0, st>>>(a);
+  const bool batched = a.t == 8 && a.beta == 2 && (a.N == 1024 || a.N == 2048);
+  if (batched) {
+    dim3 g((uint32_t)((count + KC - 1) / KC), (a.n + 1 + 255) / 256);
+    if (a.N == 1024) keyswitch_batched_kernel<1024><<<g, 256, 0, st>>>(a, (uint32_t)count);
+    else keyswitch_batched_kernel<2048><<<g, 256, 0, st>>>(a, (uint32_t)count);
+  } else {
+    dim3 g((uint32_t)count, (a.n + 1 + 255) / 256);
+    keyswitch_kernel<<<g, 256, 0, st>>>(a);
+  }
   FS_LAUNCH_CHECK();
   return 0;
 }

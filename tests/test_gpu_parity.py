@@ -91,12 +91,26 @@ def test_pbs_lif_bit_exact(gpu_env, okeys_a):
     assert np.array_equal(_host(vv), vnew)
 
 
+def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
+    """37 neurons = 74 bootstrappings: past the fused-key-switch limit, so
+    the batched key-switch kernel runs, with a ragged last block."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m, ct = _pbs_inputs(P, sk, okeys_a, 37, first=300)
+    s2 = torch.zeros((len(m), P.n + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    F.pbs_lif(ctx, dk, 4, 2, _dev(ct), s2, vv)
+    spikes, vnew = O.lif_step(okeys_a, 4, 2, ct)
+    assert np.array_equal(_host(s2), spikes)
+    assert np.array_equal(_host(vv), vnew)
+
+
 def test_keyswitch_bit_exact(gpu_env, okeys_a):
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
-    x = synth.rng(synth.SEED_DATA, 600).integers(0, 2 ** 32, size=(5, P.N + 1),
+    x = synth.rng(synth.SEED_DATA, 600).integers(0, 2 ** 32, size=(21, P.N + 1),
                                                   dtype=np.uint64).astype(np.uint32)
-    out = torch.zeros((5, P.n + 1), dtype=torch.int32, device="cuda")
+    out = torch.zeros((21, P.n + 1), dtype=torch.int32, device="cuda")
     F.keyswitch(ctx, dk, _dev(x), out)
     assert np.array_equal(_host(out), O.keyswitch(okeys_a, x))
 
