@@ -1,0 +1,155 @@
+"""Encrypted LIF networks driven through the C ABI.
+
+The recurrence is that of Theorem 3.1 (Eq. DiscretEquation) on ciphertexts:
+    H[t] = V[t-1] + I[t]                    (fs_lwe_add / fs_lwe_linear epilogue)
+    2S[t] = FHE-Fire(H[t]) + 1              (fs_pbs_lif, Eq. FHE-Fire)
+    V[t]  = FHE-Reset(H[t])                 (fs_pbs_lif, Eq. FHE-Reset)
+with WeightSum layers between LIF layers (Sec. 4.1) and score accumulators at
+the output (the encrypted scores summed over the T steps, Sec. 5.3
+procedure).  V[0] is the all-zero ciphertext and a static encrypted image
+gives the first layer's current once.
+
+All state lives in preallocated device buffers, so one timestep can be
+captured in a HIP graph (torch.cuda.CUDAGraph) and replayed T times; every
+kernel in the step is one of the library's.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import fhesnn as F
+
+
+def _zeros(rows, width):
+    return torch.zeros((rows, width), dtype=torch.int32, device="cuda")
+
+
+@dataclass
+class LifSpec:
+    v_th: int = 4
+    tau: int = 2
+
+
+class StepGraph:
+    """Runs `fn` eagerly once (so test polynomials and scratch are in place),
+    then captures it into a HIP graph; `replay()` replays it."""
+
+    def __init__(self, fn, capture: bool):
+        self.fn = fn
+        self.graph = None
+        self.capture = capture
+
+    def run(self):
+        if not self.capture:
+            self.fn()
+            return
+        if self.graph is None:
+            # the first step runs eagerly: it fills the caches the capture needs
+            self.fn()
+            torch.cuda.synchronize()
+            self.graph = torch.cuda.CUDAGraph()
+            self._pending = True
+            return
+        if self._pending:
+            with torch.cuda.graph(self.graph):
+                self.fn()
+            self._pending = False
+        self.graph.replay()
+
+
+class LifLayerNet:
+    """One LIF layer fed by a static current I = W x (the tiny LIF workload)."""
+
+    def __init__(self, ctx, dk, W: np.ndarray, lif: LifSpec = LifSpec(), capture: bool = False):
+        self.ctx, self.dk, self.lif = ctx, dk, lif
+        P = dk.params
+        self.width = P.n + 1
+        self.W = F.to_device(np.ascontiguousarray(W, np.int32))
+        self.O = W.shape[0]
+        self.I = _zeros(self.O, self.width)
+        self.H = _zeros(self.O, self.width)
+        self.V = _zeros(self.O, self.width)
+        self.S = _zeros(self.O, self.width)
+        self.capture = capture
+        self.pbs_count = 0
+        ctx.reserve(P.N, 2 * self.O)
+
+    def _step(self):
+        F.lwe_add(self.ctx, self.V, self.I, self.H)
+        F.pbs_lif(self.ctx, self.dk, self.lif.v_th, self.lif.tau, self.H, self.S, self.V)
+
+    def run(self, x_ct: torch.Tensor, T: int, record: bool = True):
+        """x_ct: device [inputs][n+1].  Returns per-step host copies (H, 2S, V)."""
+        F.lwe_linear(self.ctx, self.W, x_ct, self.I)
+        self.V.zero_()
+        g = StepGraph(self._step, self.capture)
+        out = []
+        for _ in range(T):
+            g.run()
+            self.pbs_count += 2 * self.O
+            if record:
+                torch.cuda.synchronize()
+                out.append((F.to_host(self.H), F.to_host(self.S), F.to_host(self.V)))
+        return out
+
+
+class ConvSNN:
+    """conv (LIF) -> FC (LIF) -> FC score accumulators on one encrypted image."""
+
+    def __init__(self, ctx, dk, Wc, W1, W2, geom, lif: LifSpec = LifSpec(), capture: bool = False):
+        self.ctx, self.dk, self.lif = ctx, dk, lif
+        P = dk.params
+        self.width = P.n + 1
+        self.Ci, self.H, self.Wd, self.stride, self.pad = geom
+        Co, _, K, _ = Wc.shape
+        self.Ho = (self.H + 2 * self.pad - K) // self.stride + 1
+        self.Wo = (self.Wd + 2 * self.pad - K) // self.stride + 1
+        self.l1 = Co * self.Ho * self.Wo
+        self.hidden = W1.shape[0]
+        self.classes = W2.shape[0]
+        self.Wc = F.to_device(np.ascontiguousarray(Wc, np.int32))
+        self.W1 = F.to_device(np.ascontiguousarray(W1, np.int32))
+        self.W2 = F.to_device(np.ascontiguousarray(W2, np.int32))
+        w = self.width
+        self.I1, self.H1, self.V1, self.S1 = (_zeros(self.l1, w) for _ in range(4))
+        self.H2, self.V2, self.S2 = (_zeros(self.hidden, w) for _ in range(3))
+        self.score = _zeros(self.classes, w)
+        self.capture = capture
+        self.pbs_count = 0
+        ctx.reserve(P.N, 2 * max(self.l1, self.hidden))
+
+    def _step(self):
+        c, dk, L = self.ctx, self.dk, self.lif
+        F.lwe_add(c, self.V1, self.I1, self.H1)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        F.lwe_linear(c, self.W2, self.S2, self.score, add=self.score)
+
+    def run(self, px_ct: torch.Tensor, T: int, record: bool = False):
+        """px_ct: device [Ci*H*Wd][n+1].  Returns the score ciphertexts (host)
+        and, if record, per-step host copies of every state buffer."""
+        F.lwe_conv2d(self.ctx, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd,
+                     self.stride, self.pad)
+        for b in (self.V1, self.V2, self.score):
+            b.zero_()
+        g = StepGraph(self._step, self.capture)
+        steps = []
+        for _ in range(T):
+            g.run()
+            self.pbs_count += 2 * (self.l1 + self.hidden)
+            if record:
+                torch.cuda.synchronize()
+                steps.append({k: F.to_host(getattr(self, k)) for k in
+                              ("H1", "S1", "V1", "H2", "S2", "V2", "score")})
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
+
+def pbs_count_paper_csnn(T: int) -> int:
+    """Bootstrappings per image of the paper's CSNN (Table 1): 2 per LIF
+    neuron per step over the 10x12x12, 160 and 10 LIF neurons."""
+    return (1440 * 2 + 2 * 160 + 2 * 10) * T

@@ -1,0 +1,88 @@
+"""Encrypted networks on the GPU against the oracle (bit-exact ciphertexts) and
+against the plaintext integer SNN (decrypted spikes), eagerly and with each
+timestep replayed from a captured HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from paper_2309_09025_amd import fhesnn as F
+from paper_2309_09025_amd import network as NW
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("capture", [False, True])
+def test_tiny_lif_layer_bit_exact_and_spike_for_spike(gpu_env, okeys_a, capture):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.TinyLIF()
+    x, W = cfg.data()
+    ct = F.encrypt(sk, x, synth.SEED_ENC)
+    net = NW.LifLayerNet(ctx, dk, W, NW.LifSpec(cfg.vth, cfg.tau), capture=capture)
+    got = net.run(F.to_device(ct), cfg.T)
+    assert net.pbs_count == 2 * cfg.neurons * cfg.T
+    I_ct = O.lwe_linear(W, O.encrypt(O.SHAPE_A, okeys_a.s, x, synth.SEED_ENC))
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I_ct, cfg.vth, cfg.tau, cfg.T)
+    pH, pS, pV = O.plain_lif_layer_run(P.p, W.astype(np.int64) @ x, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        H, S, V = got[t]
+        assert np.array_equal(H, Hs[t]) and np.array_equal(S, Ss[t]) and np.array_equal(V, Vs[t]), t
+        assert np.array_equal(F.decrypt(sk, S), O.centred(P.p, pS[t])), t
+        assert np.array_equal(F.decrypt(sk, V), O.centred(P.p, pV[t])), t
+
+
+@pytest.mark.parametrize("capture", [False, True])
+def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, capture):
+    """The conv -> FC -> FC topology at a size the oracle runs end to end."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.CONV_SNN_MINI
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=capture)
+    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    assert net.pbs_count == cfg.pbs_count()
+    _, osteps = O.conv_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
+                               Wc, W1, W2, geom, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert np.array_equal(steps[t][k], osteps[t][k]), (t, k)
+    assert np.array_equal(score, osteps[-1]["score"])
+
+
+def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
+    """Config 3 at full size (28x28 image, conv 1->8 5x5 s2 p2, FC 1568->256,
+    FC 256->10, T = 4), graph-replayed.  The oracle recomputes the conv
+    current and the complete T-step chains of sampled first-layer neurons
+    (each neuron's chain depends only on its own current); every layer-2
+    output is checked by properties that hold at any size."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.CONV_SNN
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=True)
+    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    assert net.pbs_count == cfg.pbs_count() == 14592
+    octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
+    I1 = O.lwe_conv2d(Wc, octs, cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    sample = [0, 1, 97, 784, 1567]
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I1[sample], cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        assert np.array_equal(steps[t]["H1"][sample], Hs[t]), t
+        assert np.array_equal(steps[t]["S1"][sample], Ss[t]), t
+        assert np.array_equal(steps[t]["V1"][sample], Vs[t]), t
+        # every bootstrapped output decrypts to a value of its program function
+        s2 = F.decrypt(sk, steps[t]["S2"])
+        v2 = F.decrypt(sk, steps[t]["V2"])
+        assert set(np.unique(s2)) <= {0, 2}
+        assert set(np.unique(v2)) <= {0, 1, 2, -1, -2}
+        s1 = F.decrypt(sk, steps[t]["S1"])
+        assert set(np.unique(s1)) <= {0, 2}
+    # layer-2 input is the WeightSum of the layer-1 spikes plus V2: linear
+    want_h2 = O.lwe_linear(W1, steps[0]["S1"])
+    assert np.array_equal(steps[0]["H2"], want_h2)
+    want_score = O.lwe_linear(W2, steps[1]["S2"], add=steps[0]["score"])
+    assert np.array_equal(steps[1]["score"], want_score)
