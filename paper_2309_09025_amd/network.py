@@ -153,3 +153,87 @@ def pbs_count_paper_csnn(T: int) -> int:
     """Bootstrappings per image of the paper's CSNN (Table 1): 2 per LIF
     neuron per step over the 10x12x12, 160 and 10 LIF neurons."""
     return (1440 * 2 + 2 * 160 + 2 * 10) * T
+
+
+class UnevenBatch:
+    """Many images, each with its own number of steps T_i and hidden width
+    H_i (one network per width), evaluated together: per timestep one
+    fs_pbs_lif launch bootstraps the first-layer neurons of every still
+    active image and one more the hidden neurons of all of them.  Images are
+    kept in descending T order so the active ones form a prefix of every
+    buffer.  Each distinct active set is captured once as a HIP graph and
+    replayed for as many steps as it lasts."""
+
+    def __init__(self, ctx, dk, Wc, nets: dict, geom, lif: LifSpec = LifSpec(),
+                 capture: bool = True):
+        """nets: hidden width -> (W1 [H][l1], W2 [classes][H])."""
+        self.ctx, self.dk, self.lif = ctx, dk, lif
+        P = dk.params
+        self.width = P.n + 1
+        self.Ci, self.Hh, self.Wd, self.stride, self.pad = geom
+        Co, _, K, _ = Wc.shape
+        Ho = (self.Hh + 2 * self.pad - K) // self.stride + 1
+        Wo = (self.Wd + 2 * self.pad - K) // self.stride + 1
+        self.l1 = Co * Ho * Wo
+        self.Wc = F.to_device(np.ascontiguousarray(Wc, np.int32))
+        self.nets = {h: (F.to_device(np.ascontiguousarray(a, np.int32)),
+                         F.to_device(np.ascontiguousarray(b, np.int32))) for h, (a, b) in nets.items()}
+        self.classes = next(iter(nets.values()))[1].shape[0]
+        self.capture = capture
+        self.pbs_count = 0
+
+    def run(self, px_cts, Ts, Hs):
+        """px_cts: list of device [Ci*H*Wd][n+1]; returns host score
+        ciphertexts per image (input order) and the bootstrapping count."""
+        ctx, w = self.ctx, self.width
+        order = sorted(range(len(px_cts)), key=lambda i: (-Ts[i], i))
+        B = len(order)
+        Ts_s = [int(Ts[i]) for i in order]
+        Hs_s = [int(Hs[i]) for i in order]
+        off2 = np.concatenate([[0], np.cumsum(Hs_s)]).astype(int)
+        l1 = self.l1
+        I1, H1, V1, S1 = (_zeros(B * l1, w) for _ in range(4))
+        H2, V2, S2 = (_zeros(int(off2[-1]), w) for _ in range(3))
+        score = _zeros(B * self.classes, w)
+        self.ctx.reserve(self.dk.params.N, 2 * max(B * l1, int(off2[-1])))
+        for k, i in enumerate(order):
+            F.lwe_conv2d(ctx, self.Wc, px_cts[i], I1[k * l1:(k + 1) * l1], self.Ci, self.Hh, self.Wd,
+                         self.stride, self.pad)
+        L = self.lif
+
+        def make_step(active):
+            n1 = active * l1
+            n2 = int(off2[active])
+
+            def step():
+                F.lwe_add(ctx, V1[:n1], I1[:n1], H1[:n1])
+                F.pbs_lif(ctx, self.dk, L.v_th, L.tau, H1[:n1], S1[:n1], V1[:n1])
+                for k in range(active):
+                    W1, W2 = self.nets[Hs_s[k]]
+                    a, b = int(off2[k]), int(off2[k + 1])
+                    F.lwe_linear(ctx, W1, S1[k * l1:(k + 1) * l1], H2[a:b], add=V2[a:b])
+                F.pbs_lif(ctx, self.dk, L.v_th, L.tau, H2[:n2], S2[:n2], V2[:n2])
+                for k in range(active):
+                    W1, W2 = self.nets[Hs_s[k]]
+                    a, b = int(off2[k]), int(off2[k + 1])
+                    sc = score[k * self.classes:(k + 1) * self.classes]
+                    F.lwe_linear(ctx, W2, S2[a:b], sc, add=sc)
+            return step, 2 * (n1 + n2)
+
+        t = 0
+        Tmax = Ts_s[0] if B else 0
+        while t < Tmax:
+            active = sum(1 for x in Ts_s if x > t)
+            span = min(x for x in Ts_s if x > t) - t  # steps this active set lasts
+            fn, count = make_step(active)
+            g = StepGraph(fn, self.capture)
+            for _ in range(span):
+                g.run()
+                self.pbs_count += count
+            t += span
+        torch.cuda.synchronize()
+        host = F.to_host(score).reshape(B, self.classes, w)
+        out = [None] * B
+        for k, i in enumerate(order):
+            out[i] = host[k]
+        return out

@@ -86,3 +86,30 @@ def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
     assert np.array_equal(steps[0]["H2"], want_h2)
     want_score = O.lwe_linear(W2, steps[1]["S2"], add=steps[0]["score"])
     assert np.array_equal(steps[1]["score"], want_score)
+
+
+def test_uneven_batch_equals_images_alone(gpu_env):
+    """Images of different T and hidden width evaluated together give the
+    same score ciphertexts, byte for byte, as each image evaluated alone."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    base = synth.CONV_SNN_MINI
+    widths = (8, 12)
+    nets = {}
+    for h in widths:
+        cfg = synth.ConvSNN(**{**base.__dict__, "hidden": h})
+        _, Wc, W1, W2 = cfg.data()
+        nets[h] = (W1, W2)
+    geom = (base.Ci, base.H, base.Wd, base.stride, base.pad)
+    Ts = [2, 3, 1, 3]
+    Hs = [8, 12, 12, 8]
+    pxs = [synth.ConvSNN(**{**base.__dict__}).data(image_stream=k)[0] for k in range(4)]
+    cts = [F.to_device(F.encrypt(sk, px, synth.SEED_ENC, 1000 * k)) for k, px in enumerate(pxs)]
+    batch = NW.UnevenBatch(ctx, dk, Wc, nets, geom, NW.LifSpec(base.vth, base.tau))
+    got = batch.run(cts, Ts, Hs)
+    assert batch.pbs_count == sum(2 * t * (base.l1 + h) for t, h in zip(Ts, Hs))
+    for k in range(4):
+        alone = NW.ConvSNN(ctx, dk, Wc, nets[Hs[k]][0], nets[Hs[k]][1], geom,
+                           NW.LifSpec(base.vth, base.tau), capture=False)
+        score, _ = alone.run(cts[k], Ts[k])
+        assert np.array_equal(got[k], score), k

@@ -142,3 +142,32 @@ def test_lwe_conv2d_bit_exact(gpu_env, geom):
     y = torch.zeros((Co * Ho * Wo, 631), dtype=torch.int32, device="cuda")
     F.lwe_conv2d(ctx, _dev(W), _dev(x), y, Ci, H, Wd, st, pd)
     assert np.array_equal(_host(y), O.lwe_conv2d(W, x, Ci, H, Wd, st, pd))
+
+
+@pytest.mark.parametrize("keyswitch", [False, True])
+def test_pbs_shape_b_bit_exact(gpu_env, okeys_b, keyswitch):
+    """Second shape: N = 2048, l = 2, Bg = 2^10, p = 64 (the key is split in
+    two 16-bit halves inside the transform)."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(1)
+    m, ct = _pbs_inputs(P, sk, okeys_b, 6, first=400)
+    f = O.lut_fire(P.p, 4)
+    width = P.n + 1 if keyswitch else P.N + 1
+    out = torch.zeros((len(m), width), dtype=torch.int32, device="cuda")
+    F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=keyswitch)
+    want = O.pbs(okeys_b, O.test_poly(P.N, P.p, f), ct, keyswitch=keyswitch)
+    assert np.array_equal(_host(out), want)
+
+
+def test_shape_b_lif_batched_key_switch_bit_exact(gpu_env, okeys_b):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(1)
+    m, ct = _pbs_inputs(P, sk, okeys_b, 35, first=500)
+    s2 = torch.zeros((len(m), P.n + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    F.pbs_lif(ctx, dk, 4, 2, _dev(ct), s2, vv)
+    # the oracle on a sample of the 70 bootstrappings (each takes seconds)
+    idx = [0, 17, 34]
+    spikes, vnew = O.lif_step(okeys_b, 4, 2, ct[idx])
+    assert np.array_equal(_host(s2)[idx], spikes)
+    assert np.array_equal(_host(vv)[idx], vnew)
