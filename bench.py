@@ -27,12 +27,13 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic work of one bootstrapping, counted on the textbook radix-2
 # negacyclic transform: per CMux step (k+1) l forward and k+1 inverse
-# N-point transforms of N/2 log2 N butterflies (1 modular product + 1 sum +
-# 1 difference each) and (k+1)^2 l N pointwise products (1 modular product
-# + 1 accumulate each); n CMux steps per bootstrapping.  One modular
-# product is 5 binary64 VALU instructions (mul, fma, mul, rndne, fma), so a
-# butterfly is 7 and a pointwise multiply-accumulate 6 instructions.
-MODMUL_OPS, BFLY_OPS, MAC_OPS = 5, 7, 6
+# N-point transforms of N/2 log2 N butterflies and (k+1)^2 l N pointwise
+# multiply-accumulates; n CMux steps per bootstrapping.  In the exact
+# binary64 residue arithmetic a modular product is 5 VALU instructions
+# (mul, fma, mul, rndne, fma) plus 1 to join its exact halves, so a
+# butterfly (product, sum, difference) is at least 8 instructions and a
+# multiply-accumulate 7.
+MODMUL_OPS, BFLY_OPS, MAC_OPS = 6, 8, 7
 
 
 def alg_ops_per_pbs(n, N, l):

@@ -39,6 +39,7 @@ struct fs_ctx {
   std::map<std::vector<int32_t>, uint32_t*> tpoly;
   // NTT tables per ring degree for fs_ntt_polymul
   std::map<uint32_t, double*> tables;
+  std::map<uint32_t, fs::UniTw> table_uni;
   // blind-rotation kernel variant per ring degree (chosen by the tuner)
   std::map<uint32_t, int> br_variant;
   // batches up to this many bootstrappings key-switch inside the blind
@@ -584,15 +585,18 @@ int fs_ntt_polymul(fs_ctx* ctx, uint32_t N, uint32_t R, int32_t dmax, const int3
   auto it = ctx->tables.find(N);
   double *f = nullptr, *iv = nullptr, *po = nullptr;
   if (it == ctx->tables.end()) {
-    int rc = upload_tables(N, &f, &iv, &po);
+    UniTw uni{};
+    int rc = upload_tables(N, &f, &iv, &po, &uni);
     if (rc) return rc;
     ctx->tables[N] = f;
+    ctx->table_uni[N] = uni;
   } else {
     f = it->second;
   }
   iv = f + N;
   po = f + N + N / 2;
-  return launch_rc(launch_polymul(N, d, b, R, out, f, iv, po, as_stream(stream)), "polymul");
+  return launch_rc(launch_polymul(N, d, b, R, out, f, iv, po, ctx->table_uni[N], as_stream(stream)),
+                   "polymul");
 }
 
 }  // extern "C"

@@ -44,7 +44,8 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, b
                         hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
-                   const double* tw, const double* itw, const double* post, hipStream_t st);
+                   const double* tw, const double* itw, const double* post, const UniTw& uni,
+                   hipStream_t st);
 
 int launch_lwe_linear(const int32_t* W, size_t O, size_t I, uint32_t dim, const uint32_t* x,
                       const uint32_t* add, uint32_t* y, hipStream_t st);

@@ -253,7 +253,8 @@ __device__ __forceinline__ void load_fwd_lane(double* w, const double* __restric
   }
 }
 
-template <int LOGN, int LO, int SHI, int SLO>
+// Forward stages SHI down to SLO of the round whose top stage is RHI.
+template <int LOGN, int LO, int RHI, int SHI, int SLO>
 __device__ __forceinline__ void fwd_stages_reg(double x[16], const double* w) {
 #pragma unroll
   for (int s = SHI; s >= SLO; --s) {
@@ -262,7 +263,7 @@ __device__ __forceinline__ void fwd_stages_reg(double x[16], const double* w) {
     for (int r = 0; r < 16; ++r) {
       if (r & (1 << b)) continue;
       const int r2 = r | (1 << b);
-      const double m = mulmod(x[r2], w[fwd_lane_off(LO, SHI, s) + (r >> (b + 1))]);
+      const double m = mulmod(x[r2], w[fwd_lane_off(LO, RHI, s) + (r >> (b + 1))]);
       x[r2] = x[r] - m;
       x[r] = x[r] + m;
     }
@@ -287,25 +288,33 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
   }
 }
 
-// Forward transform with register roots (same result as ntt_fwd).  The
-// per-thread roots of rounds B and C are requested one round ahead.
+// Forward transform with register roots: the transform of ntt_fwd with a
+// shorter reduction schedule for digit inputs (|x| <= 512): five stages,
+// reduce, four stages, reduce, the remaining one or two stages.  The output
+// is NOT reduced: |x| < 1.14 P (N = 1024) or 1.97 P (N = 2048), which keeps
+// a sum of 2l products with reduced key values below 5 P < 2^53 (the bound
+// check of this schedule is in tests/test_ntt_bounds.py).  The per-thread
+// roots of rounds B and C are requested one round ahead.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
                                             const double* __restrict__ tw, int t) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
+  constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
   double wb[R::FB];
-  load_fwd_lane<LOGN, S::LOB, LOGN - 5, 4>(wb, tw, t);
+  load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb, tw, t);
   fwd_roundA_uni<LOGN>(x, u);
-  reduce16<S::N>(x);
   exchange<LOGN, S::LOA, S::LOB>(x, lds, t);
   double wc[R::FC];
   load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);
-  fwd_stages_reg<LOGN, S::LOB, LOGN - 5, 4>(x, wb);
+  fwd_stages_reg<LOGN, S::LOB, BHI, BHI, BHI>(x, wb);  // fifth stage
   reduce16<S::N>(x);
+  fwd_stages_reg<LOGN, S::LOB, BHI, BHI - 1, 4>(x, wb);
   exchange<LOGN, S::LOB, 0>(x, lds, t);
-  fwd_stages_reg<LOGN, 0, 3, 0>(x, wc);
+  // stages 3 .. LOGN-9 complete the second segment of four
+  fwd_stages_reg<LOGN, 0, 3, 3, LOGN - 9>(x, wc);
   reduce16<S::N>(x);
+  fwd_stages_reg<LOGN, 0, 3, LOGN - 10, 0>(x, wc);
 }
 
 template <int LOGN>
@@ -340,7 +349,8 @@ __device__ __forceinline__ void load_inv_tw(double* wi, const double* __restrict
   for (int r = 0; r < 16; ++r) wi[R::IB + R::IA + r] = post[t + S::TP * r];
 }
 
-template <int LOGN, int LO, int SLO, int SHI>
+// Inverse stages SLO up to SHI of the round whose first stage is RLO.
+template <int LOGN, int LO, int RLO, int SLO, int SHI>
 __device__ __forceinline__ void inv_stages_reg(double x[16], const double* w) {
 #pragma unroll
   for (int s = SLO; s <= SHI; ++s) {
@@ -349,7 +359,7 @@ __device__ __forceinline__ void inv_stages_reg(double x[16], const double* w) {
     for (int r = 0; r < 16; ++r) {
       if (r & (1 << b)) continue;
       const int r2 = r | (1 << b);
-      const double m = mulmod(x[r2], w[inv_lane_off(LO, SLO, s) + (r & ((1 << b) - 1))]);
+      const double m = mulmod(x[r2], w[inv_lane_off(LO, RLO, s) + (r & ((1 << b) - 1))]);
       x[r2] = x[r] - m;
       x[r] = x[r] + m;
     }
@@ -373,34 +383,50 @@ __device__ __forceinline__ void inv_roundC_uni(double x[16], const UniTw& u, int
   }
 }
 
-// Inverse transform with register roots (same result as ntt_inv).  The
-// per-thread roots of each round are requested one round ahead, so their
-// latency overlaps the previous round.
+// Inverse transform with register roots: the transform of ntt_inv with
+// reductions before stages 0, 3 and 7 only (stages 0..2 contain butterflies
+// whose root is 1 and double the bound); ends with the twist psi^-j N^-1 and
+// a reduction, giving the exact centred residue.  The per-thread roots of
+// each round are requested one round ahead.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const UniTw& u,
                                             const double* __restrict__ itw,
                                             const double* __restrict__ post, int t) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
+  constexpr int BHI = LOGN - 5;  // round B': stages 4..BHI, round A': BHI+1..LOGN-1
   double wb[R::IB];
-  load_inv_lane<LOGN, S::LOB, 4, LOGN - 5>(wb, itw, t);
+  load_inv_lane<LOGN, S::LOB, 4, BHI>(wb, itw, t);
   reduce16<S::N>(x);
-  inv_roundC_uni<LOGN>(x, u, 0, 1);  // < 2.1 P
+  inv_roundC_uni<LOGN>(x, u, 0, 2);
   reduce16<S::N>(x);
-  inv_roundC_uni<LOGN>(x, u, 2, 3);  // < 2.3 P
-  reduce16<S::N>(x);
+  inv_roundC_uni<LOGN>(x, u, 3, 3);
   exchange<LOGN, 0, S::LOB>(x, lds, t);
   double wa[R::IA];
   load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wa, itw, t);
-  inv_stages_reg<LOGN, S::LOB, 4, LOGN - 5>(x, wb);  // < 3.1 P
-  reduce16<S::N>(x);
+  inv_stages_reg<LOGN, S::LOB, 4, 4, BHI>(x, wb);
   exchange<LOGN, S::LOB, S::LOA>(x, lds, t);
   double wp[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) wp[r] = post[t + S::TP * r];
-  inv_stages_reg<LOGN, S::LOA, LOGN - 4, LOGN - 1>(x, wa);  // < 4.4 P
+  if constexpr (LOGN - 4 <= 6) {  // N = 1024: stage 6 is the first of round A'
+    inv_stages_reg<LOGN, S::LOA, LOGN - 4, LOGN - 4, 6>(x, wa);
+    reduce16<S::N>(x);
+    inv_stages_reg<LOGN, S::LOA, LOGN - 4, 7, LOGN - 1>(x, wa);
+  } else {  // N = 2048: stages 3..6 end round B'
+    reduce16<S::N>(x);
+    inv_stages_reg<LOGN, S::LOA, LOGN - 4, LOGN - 4, LOGN - 1>(x, wa);
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = redc(mulmod(x[r], wp[r]));
+}
+
+// Low 32 bits of an integer-valued double e with |e| < 2^51: e + 1.5 * 2^52
+// lies in [2^52, 2^53), where the unit in the last place is 1, so the low
+// word of its encoding is (e + 2^51) mod 2^32 = e mod 2^32.
+__device__ __forceinline__ uint32_t low32_magic(double e) {
+  const double y = e + 6755399441055744.0;  // 1.5 * 2^52
+  return (uint32_t)__double_as_longlong(y);
 }
 
 // Low 32 bits of an integer-valued double of magnitude < 2^52.

@@ -162,7 +162,8 @@ blind_rotate_kernel(BrArgs a) {
           }
       }
     }
-    // inverse transforms; p* hold sums of 2L products, each < 0.65 P
+    // inverse transforms; p* hold sums of 2L products of transformed digits
+    // (|x| < 2 P, not reduced) with reduced key values: < 5 P
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       uint32_t upd[16];
@@ -172,7 +173,7 @@ blind_rotate_kernel(BrArgs a) {
         ntt_inv_reg<LOGN>(y, lds, a.uni, a.inv_tw, a.post, t);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint32_t part = low32(y[r]);
+          const uint32_t part = low32_magic(y[r]);
           upd[r] = lb == 0 ? part : upd[r] + (part << 16);
         }
       }
@@ -334,12 +335,14 @@ keyswitch_batched_kernel(KsArgs a, uint32_t count) {
 }
 
 // ---------------------------------------------------------------------------
-// Negacyclic product check: out = sum_r d_r b_r through the same transform.
+// Negacyclic product check: out = sum_r d_r b_r through the transforms the
+// blind rotation uses (register-root forward transform of the digit side,
+// table forward transform of the key side, register-root inverse).
 template <int LOGN, int LIMBS>
 __global__ void __launch_bounds__(NttShape<LOGN>::TP)
 polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, uint32_t R,
                uint32_t* __restrict__ out, const double* __restrict__ tw,
-               const double* __restrict__ itw, const double* __restrict__ post) {
+               const double* __restrict__ itw, const double* __restrict__ post, UniTw uni) {
   using S = NttShape<LOGN>;
   __shared__ double lds[S::LDS_DOUBLES];
   const int t = threadIdx.x;
@@ -352,7 +355,7 @@ polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, ui
     double x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = (double)d[(size_t)q * S::N + t + S::TP * r];
-    ntt_fwd<LOGN>(x, lds, tw, t);
+    ntt_fwd_reg<LOGN>(x, lds, uni, tw, t);
 #pragma unroll
     for (int lb = 0; lb < LIMBS; ++lb) {
       double y[16];
@@ -368,16 +371,20 @@ polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, ui
       ntt_fwd<LOGN>(y, lds, tw, t);
       // y is in round-C mapping like x: pointwise products line up
 #pragma unroll
-      for (int r = 0; r < 16; ++r) accv[lb][r] = redc(accv[lb][r] + mulmod(x[r], y[r]));
+      for (int r = 0; r < 16; ++r) {
+        // as in the blind rotation: up to 2l products summed unreduced
+        const double s = accv[lb][r] + mulmod(x[r], y[r]);
+        accv[lb][r] = (q % 6 == 5) ? redc(s) : s;
+      }
     }
   }
   uint32_t res[16];
 #pragma unroll
   for (int lb = 0; lb < LIMBS; ++lb) {
-    ntt_inv<LOGN>(accv[lb], lds, itw, post, t);
+    ntt_inv_reg<LOGN>(accv[lb], lds, uni, itw, post, t);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint32_t part = low32(accv[lb][r]);
+      const uint32_t part = low32_magic(accv[lb][r]);
       res[r] = lb == 0 ? part : res[r] + (part << 16);
     }
   }
@@ -463,9 +470,10 @@ int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {
 }
 
 int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
-                   const double* tw, const double* itw, const double* post, hipStream_t st) {
-  if (N == 1024) polymul_kernel<10, 1><<<1, 64, 0, st>>>(d, b, R, out, tw, itw, post);
-  else if (N == 2048) polymul_kernel<11, 2><<<1, 128, 0, st>>>(d, b, R, out, tw, itw, post);
+                   const double* tw, const double* itw, const double* post, const UniTw& uni,
+                   hipStream_t st) {
+  if (N == 1024) polymul_kernel<10, 1><<<1, 64, 0, st>>>(d, b, R, out, tw, itw, post, uni);
+  else if (N == 2048) polymul_kernel<11, 2><<<1, 128, 0, st>>>(d, b, R, out, tw, itw, post, uni);
   else return -1;
   FS_LAUNCH_CHECK();
   return 0;
