@@ -132,7 +132,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll 1
       for (int lv = 0; lv < L; ++lv) {
         // request this digit row's key slice before the transform (PREF) or
-        // after it (fewer live registers)
+        // after it, in two halves (fewer live registers)
         const double* row = bsk_i + (size_t)(c * L + lv) * 16 * TP * G;
         double g[16][G];
         if (PREF) {
@@ -149,10 +149,20 @@ blind_rotate_kernel(BrArgs a) {
         ntt_fwd_reg<LOGN>(x, lds, a.uni, a.fwd_tw, t);
         if (!PREF) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r)
+          for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
-        }
+            for (int r = 8 * h; r < 8 * h + 8; ++r)
+#pragma unroll
+              for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
+#pragma unroll
+            for (int r = 8 * h; r < 8 * h + 8; ++r)
+#pragma unroll
+              for (int lb = 0; lb < LIMBS; ++lb) {
+                p0[lb][r] += mulmod(x[r], g[r][lb]);
+                p1[lb][r] += mulmod(x[r], g[r][LIMBS + lb]);
+              }
+          }
+        } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
 #pragma unroll
@@ -160,6 +170,7 @@ blind_rotate_kernel(BrArgs a) {
             p0[lb][r] += mulmod(x[r], g[r][lb]);
             p1[lb][r] += mulmod(x[r], g[r][LIMBS + lb]);
           }
+        }
       }
     }
     // inverse transforms; p* hold sums of 2L products of transformed digits
@@ -418,7 +429,8 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 }
 
 // Kernel variants the tuner chooses from: (key-slice prefetch, minimum waves
-// per SIMD the register allocation must allow).
+// per SIMD the register allocation must allow).  N = 1024: 0 = (after, 2),
+// 1 = (before, 1), 2 = (after, 3), 3 = (after, 1).
 int blind_rotate_variants() { return 4; }
 
 template <bool KS>
@@ -428,7 +440,7 @@ static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipS
     switch (variant) {
       case 0: blind_rotate_kernel<10, 3, 7, 1, false, 2, KS><<<g, 64, 0, st>>>(a); break;
       case 1: blind_rotate_kernel<10, 3, 7, 1, true, 1, KS><<<g, 64, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<10, 3, 7, 1, true, 2, KS><<<g, 64, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<10, 3, 7, 1, false, 3, KS><<<g, 64, 0, st>>>(a); break;
       case 3: blind_rotate_kernel<10, 3, 7, 1, false, 1, KS><<<g, 64, 0, st>>>(a); break;
       default: return -2;
     }
