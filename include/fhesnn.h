@@ -208,6 +208,28 @@ FS_API int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const ui
 FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
                uint32_t* spike2_out, uint32_t* v_out, void* stream);
 
+/* One contiguous range of LIF neurons of one client for fs_pbs_lif_ranges:
+ * its evaluation key and its h / spike2_out / v_out rows (as in
+ * fs_pbs_lif), count neurons. */
+typedef struct fs_lif_range {
+  const fs_devkey* key;
+  const uint32_t* h;
+  uint32_t* spike2_out;
+  uint32_t* v_out;
+  size_t count;
+} fs_lif_range;
+
+/* fs_pbs_lif over many ranges in one blind-rotation launch (continuous
+ * batching across requests and clients): every neuron of every range is
+ * bootstrapped with its own range's key; results are bit-identical to one
+ * fs_pbs_lif call per range.  All keys must share one parameter set and
+ * device; ranges of one key are key-switched together.  ranges: host
+ * [nranges].  The context's scratch and range table are reused by the next
+ * call: calls on one context must not overlap (use one context per
+ * stream). */
+FS_API int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
+                             size_t nranges, void* stream);
+
 /* Key switching z -> s alone (Sec. 2.1, Key Switching step).
  * in: dev [B][N+1] under z; out: dev [B][n+1] under s. */
 FS_API int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,

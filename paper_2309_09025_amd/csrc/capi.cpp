@@ -45,6 +45,10 @@ struct fs_ctx {
   // batches up to this many bootstrappings key-switch inside the blind
   // rotation kernel; larger ones use the batched key-switch kernel
   size_t fuse_max_jobs = 64;
+  // device copy of the range table of the last multi-key launch
+  fs::JobRange* ranges = nullptr;
+  size_t ranges_cap = 0;
+  std::vector<fs::JobRange> ranges_host;
 };
 
 namespace fs {
@@ -398,6 +402,7 @@ int fs_ctx_destroy(fs_ctx* ctx) {
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
   if (ctx->ext) (void)hipFree(ctx->ext);
+  if (ctx->ranges) (void)hipFree(ctx->ranges);
   for (auto& kv : ctx->tpoly) (void)hipFree(kv.second);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   delete ctx;
@@ -551,6 +556,109 @@ int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32
   if (rc) return rc;
   const uint32_t add[2] = {delta_of(p), 0u};  // 2S = bootstrap_Fire + 1
   return run_pbs(ctx, dk, tp, 2, h, B, spike2_out, v_out, add, 1, as_stream(stream));
+}
+
+int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
+                      size_t nranges, void* stream) {
+  if (!ctx || !lif || (nranges && !ranges)) return fail(FS_EINVAL, "fs_pbs_lif_ranges: null argument");
+  // order: ranges of one key adjacent (stable), empty ranges dropped
+  std::vector<size_t> order;
+  for (size_t k = 0; k < nranges; ++k) {
+    const fs_lif_range& r = ranges[k];
+    if (r.count == 0) continue;
+    if (!r.key || !r.h || !r.spike2_out || !r.v_out)
+      return fail(FS_EINVAL, "fs_pbs_lif_ranges: null pointer in a range");
+    order.push_back(k);
+  }
+  if (order.empty()) return FS_OK;
+  const fs_params& P = ranges[order[0]].key->prm;
+  for (size_t k : order) {
+    const fs_params& Q = ranges[k].key->prm;
+    if (Q.n != P.n || Q.N != P.N || Q.l != P.l || Q.bg_bit != P.bg_bit || Q.p != P.p ||
+        Q.ks_t != P.ks_t || Q.ks_base_bit != P.ks_base_bit)
+      return fail(FS_EPARAM, "fs_pbs_lif_ranges: keys of different parameter sets");
+    if (ranges[k].key->device != ctx->device)
+      return fail(FS_EPARAM, "fs_pbs_lif_ranges: a key lives on another device");
+  }
+  if (P.ks_t != 8 || P.ks_base_bit != 2)
+    return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: needs the t = 8, base 4 key switch");
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    return (uintptr_t)ranges[x].key < (uintptr_t)ranges[y].key;
+  });
+  std::vector<int32_t> fire(P.p), reset(P.p);
+  int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
+  if (rc) return rc;
+  rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
+  if (rc) return rc;
+  auto& host = ctx->ranges_host;
+  host.clear();
+  uint64_t total = 0;
+  for (size_t k : order) {
+    const fs_lif_range& r = ranges[k];
+    host.push_back(JobRange{r.h, r.spike2_out, r.v_out, r.key->bsk, total});
+    total += r.count;
+  }
+  if (total > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ranges: batch too large");
+  if (ctx->ranges_cap < host.size()) {
+    if (ctx->ranges) FS_HIP(hipFree(ctx->ranges));
+    ctx->ranges = nullptr;
+    ctx->ranges_cap = 0;
+    FS_HIP(hipMalloc(&ctx->ranges, host.size() * sizeof(JobRange)));
+    ctx->ranges_cap = host.size();
+  }
+  FS_HIP(hipMemcpyAsync(ctx->ranges, host.data(), host.size() * sizeof(JobRange),
+                        hipMemcpyHostToDevice, st));
+  const size_t jobs = 2 * total;
+  rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
+  if (rc) return rc;
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  BrArgs br{};
+  br.tpoly0 = tp[0];
+  br.tpoly1 = tp[1];
+  br.nlut = 2;
+  br.n = P.n;
+  br.fwd_tw = ranges[order[0]].key->fwd_tw;  // tables depend on N only
+  br.inv_tw = ranges[order[0]].key->inv_tw;
+  br.post = ranges[order[0]].key->post;
+  br.uni = ranges[order[0]].key->uni;
+  br.ext = ctx->ext;
+  br.ranges = ctx->ranges;
+  br.nranges = (uint32_t)host.size();
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, false, st), "blind rotation");
+  if (rc) return rc;
+  // one batched key switch per key over its adjacent ranges
+  size_t a = 0;
+  while (a < order.size()) {
+    size_t b = a;
+    const fs_devkey* key = ranges[order[a]].key;
+    while (b < order.size() && ranges[order[b]].key == key) ++b;
+    const uint64_t first = host[a].first;
+    const uint64_t last = b < order.size() ? host[b].first : total;
+    KsArgs ks{};
+    ks.in = ctx->ext + (size_t)(2 * first) * (P.N + 1);
+    ks.ksk = key->ksk;
+    ks.plain_add[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
+    ks.plain_add[1] = 0u;
+    ks.nlut = 2;
+    ks.n = P.n;
+    ks.N = P.N;
+    ks.t = P.ks_t;
+    ks.beta = P.ks_base_bit;
+    ks.ranges = ctx->ranges;
+    ks.nranges = (uint32_t)host.size();
+    ks.job0 = 2 * first;
+    rc = launch_rc(launch_keyswitch(ks, (size_t)(2 * (last - first)), st), "key switch");
+    if (rc) return rc;
+    a = b;
+  }
+  return FS_OK;
 }
 
 int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,

@@ -9,6 +9,29 @@
 
 namespace fs {
 
+// A contiguous range of ciphertexts bootstrapped in a multi-key launch: its
+// input and output rows and the NTT-domain key of the client it belongs
+// to.  Ranges are listed in job order; `first` is the index of the range's
+// first ciphertext among all ciphertexts of the launch.
+struct JobRange {
+  const uint32_t* in;
+  uint32_t* out0;
+  uint32_t* out1;
+  const double* bsk;
+  uint64_t first;
+};
+
+// index of the range holding ciphertext g (ranges sorted by `first`)
+__device__ __forceinline__ uint32_t find_range(const JobRange* r, uint32_t nr, uint64_t g) {
+  uint32_t lo = 0, hi = nr;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (r[mid].first <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 struct BrArgs {
   const uint32_t* in;     // [B][n+1] input samples under s
   const uint32_t* tpoly0; // [N] test polynomial of program function 0
@@ -26,6 +49,9 @@ struct BrArgs {
   uint32_t* out0;         // program function 0 outputs, [jobs/nlut][n+1]
   uint32_t* out1;         // program function 1 outputs (nlut == 2)
   uint32_t plain_add[2];  // Delta * c added to b per program function
+  // multi-key launch: per-range inputs and keys (in and bsk unused)
+  const JobRange* ranges;
+  uint32_t nranges;
 };
 
 struct KsArgs {
@@ -35,6 +61,10 @@ struct KsArgs {
   uint32_t* out1;      // program function 1 outputs (nlut == 2)
   uint32_t plain_add[2];  // Delta * c added to b per program function
   uint32_t nlut, n, N, t, beta;
+  // multi-key launch: outputs per range; sample m is job job0 + m
+  const JobRange* ranges;
+  uint32_t nranges;
+  uint64_t job0;
 };
 
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,

@@ -78,7 +78,17 @@ blind_rotate_kernel(BrArgs a) {
   const int t = threadIdx.x;
   const size_t job = blockIdx.x;
   const uint32_t n = a.n;
-  const uint32_t* ct = a.in + (job / a.nlut) * (size_t)(n + 1);
+  const uint64_t g = job / a.nlut;  // ciphertext of this job
+  const uint32_t* ct;
+  const double* __restrict__ bsk;
+  if (a.ranges) {  // multi-key launch: the range of g gives input and key
+    const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+    ct = rg.in + (g - rg.first) * (size_t)(n + 1);
+    bsk = rg.bsk;
+  } else {
+    ct = a.in + g * (size_t)(n + 1);
+    bsk = a.bsk;
+  }
   const uint32_t* v = (job % a.nlut) == 0 ? a.tpoly0 : a.tpoly1;
 
   // gadget rounding offset: sum_{j=1..L} (Bg/2) 2^{32 - j BG} + 2^{31 - L BG}
@@ -105,7 +115,6 @@ blind_rotate_kernel(BrArgs a) {
   }
   __syncthreads();
 
-  const double* __restrict__ bsk = a.bsk;
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t abar = (ct[i] + (1u << (31 - NU))) >> (32 - NU);
     if (abar == 0) continue;  // X^0 ACC - ACC = 0: every digit is zero
@@ -234,7 +243,13 @@ blind_rotate_kernel(BrArgs a) {
       }
     }
     const uint32_t lut = (uint32_t)(job % a.nlut);
-    uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (job / a.nlut) * (size_t)w1;
+    uint32_t* out;
+    if (a.ranges) {
+      const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+      out = (lut == 0 ? rg.out0 : rg.out1) + (g - rg.first) * (size_t)w1;
+    } else {
+      out = (lut == 0 ? a.out0 : a.out1) + g * (size_t)w1;
+    }
     const uint32_t bprime = acc[1][0] + a.plain_add[lut];
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
@@ -337,10 +352,17 @@ keyswitch_batched_kernel(KsArgs a, uint32_t count) {
   for (int c = 0; c < KC; ++c) {
     const size_t m = m0 + c;
     if (m >= count) break;
-    const uint32_t lut = (uint32_t)(m % a.nlut);
+    const uint32_t lut = (uint32_t)((a.job0 + m) % a.nlut);
     const uint32_t* in = a.in + m * (size_t)(N + 1);
     const uint32_t v = w == n ? acc[c] + in[N] + a.plain_add[lut] : acc[c];
-    uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * (size_t)w1;
+    const uint64_t g = (a.job0 + m) / a.nlut;
+    uint32_t* out;
+    if (a.ranges) {
+      const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+      out = (lut == 0 ? rg.out0 : rg.out1) + (g - rg.first) * (size_t)w1;
+    } else {
+      out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * (size_t)w1;
+    }
     out[w] = v;
   }
 }

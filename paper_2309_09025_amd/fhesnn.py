@@ -42,6 +42,11 @@ class CLif(ctypes.Structure):
     _fields_ = [("v_th", ctypes.c_int32), ("tau", ctypes.c_uint32)]
 
 
+class CLifRange(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("h", ctypes.c_void_p), ("spike2_out", ctypes.c_void_p),
+                ("v_out", ctypes.c_void_p), ("count", ctypes.c_size_t)]
+
+
 _vp = ctypes.c_void_p
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -84,6 +89,7 @@ SIGNATURES = {
     "fs_lwe_add": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
+    "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "fs_ntt_polymul": (_int, [_vp, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
 }
@@ -318,6 +324,15 @@ def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
     lif = CLif(v_th, tau)
     _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
                                           _dptr(spike2_out), _dptr(v_out), _stream(stream)))
+
+
+def pbs_lif_ranges(ctx: Context, v_th: int, tau: int, ranges, stream=None):
+    """ranges: iterable of (DevKey, h, spike2_out, v_out) device tensors."""
+    rs = [CLifRange(dk.h, _dptr(h).value, _dptr(s2).value, _dptr(v).value, h.shape[0])
+          for dk, h, s2, v in ranges]
+    arr = (CLifRange * max(1, len(rs)))(*rs)
+    _check("fs_pbs_lif_ranges", lib().fs_pbs_lif_ranges(ctx.h, ctypes.byref(CLif(v_th, tau)),
+                                                        arr, len(rs), _stream(stream)))
 
 
 def keyswitch(ctx: Context, dk: DevKey, x, out, stream=None):
