@@ -68,6 +68,116 @@ def _traffic(shape, batch):
     return None
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def unbatched(F, ctx, dk, fire, d_in, reps=8):
+    """The same kernel at B = 1, one launch per bootstrapping."""
+    import torch
+    P = dk.params
+    out = F.empty_ct(1, P.n + 1)
+    F.pbs(ctx, dk, fire, d_in[:1], out, keyswitch=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        F.pbs(ctx, dk, fire, d_in[k:k + 1], out, keyswitch=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"pbs_per_s": round(1.0 / dt, 2), "latency_ms": round(dt * 1e3, 3), "launches": reps}
+
+
+def _conv_nets(synth, widths):
+    nets = {}
+    for h in widths:
+        cfg = synth.ConvSNN(hidden=h)
+        _, Wc, W1, W2 = cfg.data()
+        nets[h] = (W1, W2)
+    return Wc, nets
+
+
+def single_image(F, NW, synth, ctx, dk, sk, images=3):
+    """Conv SNN on one 28x28 image at a time (T = 4, hidden 256), each
+    timestep replayed from a HIP graph; encrypted image resident in HBM."""
+    import torch
+    cfg = synth.CONV_SNN
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=True)
+    cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
+           for k in range(images + 1)]
+    net.run(cts[-1], cfg.T)  # warm (caches, graph)
+    torch.cuda.synchronize()
+    lat = []
+    for k in range(images):
+        t0 = time.perf_counter()
+        net.run(cts[k], cfg.T)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    m = sum(lat) / len(lat)
+    return {"workload": "conv SNN, 1 synthetic 28x28 image, conv 1->8 5x5 s2 p2 (LIF) -> FC 1568->256 "
+                        "(LIF) -> FC 256->10 accumulators, T=4",
+            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
+            "bootstrappings_per_image": cfg.pbs_count(),
+            "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+
+
+def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):
+    """64 images with T in {2..8} and hidden width 256 or 800, one launch per
+    layer per timestep, one HIP graph per active set."""
+    import torch
+    Ts, Hs = synth.uneven_batch(images=images)
+    Wc, nets = _conv_nets(synth, (256, 800))
+    base = synth.CONV_SNN
+    geom = (base.Ci, base.H, base.Wd, base.stride, base.pad)
+    cts = [F.to_device(F.encrypt(sk, base.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
+           for k in range(images)]
+    batch = NW.UnevenBatch(ctx, dk, Wc, nets, geom, NW.LifSpec(base.vth, base.tau))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(cts, [int(t) for t in Ts], [int(h) for h in Hs])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"{images} synthetic images, T uniform in 2..8, hidden 256 or 800",
+            "predictions_per_s": round(images / dt, 3), "seconds": round(dt, 3),
+            "bootstrappings": batch.pbs_count, "pbs_per_s": round(batch.pbs_count / dt, 1)}
+
+
+def serving(F, SV, synth, ctx, P, capacity, requests=48, clients=8, load=0.8):
+    """Poisson arrivals from 8 clients with their own resident keys; hidden
+    256/800 and T 2..8 per request; admission by a budget of 16 requests."""
+    Wc, nets = _conv_nets(synth, (256, 800))
+    base = synth.CONV_SNN
+    geom = (base.Ci, base.H, base.Wd, base.stride, base.pad)
+    srv = SV.Server(ctx, Wc, nets, geom, budget_bytes=1)
+    sks = {}
+    for c in range(clients):
+        sk, evk = F.keygen(P, 100 + c)
+        srv.register(c, evk)
+        sks[c] = sk
+    srv.budget = 16 * max(srv.request_bytes(h) for h in nets)
+    g = synth.rng(synth.SEED_DATA, 321)
+    rate = load * capacity
+    arr = SV.poisson_arrivals(requests, rate, synth.SEED_DATA)
+    reqs = []
+    for r in range(requests):
+        c = int(g.integers(0, clients))
+        T = int(g.integers(2, 9))
+        H = 256 if g.integers(0, 2) == 0 else 800
+        px = base.data(image_stream=200 + r)[0]
+        reqs.append(SV.Request(r, c, F.encrypt(sks[c], px, synth.SEED_ENC, 7000 * r), T, H,
+                               float(arr[r])))
+    srv.run(reqs, log=_log)
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    st = SV.latency_stats(reqs)
+    return {"workload": f"{requests} requests, {clients} clients with resident keys, Poisson "
+                        f"arrivals at {rate:.2f}/s ({load} x uneven-batch capacity), T 2..8, "
+                        f"hidden 256/800, admission budget 16 requests",
+            "predictions_per_s": round(requests / span, 3), "p50_latency_s": round(st["p50_s"], 3),
+            "p99_latency_s": round(st["p99_s"], 3), "bootstrappings": srv.pbs_count,
+            "resident_key_bytes": srv.key_bytes(), "ticks": srv.ticks}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +189,8 @@ def main():
                     help="bootstrappings the CPU oracle times (0: 2 per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="time every kernel variant again")
+    ap.add_argument("--no-networks", action="store_true",
+                    help="only the batched bootstrapping step (no prediction workloads)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -186,6 +298,17 @@ def main():
                          f"{cdt:.1f} s on {nt} threads",
                "parity_on_sample": bool(np.array_equal(ores, out[:S]))}
 
+    extra = {"unbatched": unbatched(F, ctx, dk, fire, d_in)}
+    if not args.no_networks and shape == 0:
+        from paper_2309_09025_amd import network as NW
+        from paper_2309_09025_amd import serve as SV
+        _log("single-image conv SNN")
+        extra["single_image"] = single_image(F, NW, synth, ctx, dk, sk)
+        _log("uneven batch of 64 images")
+        extra["uneven_batch"] = uneven_batch(F, NW, synth, ctx, dk, sk)
+        _log("serving")
+        extra["serving"] = serving(F, SV, synth, ctx, P, extra["uneven_batch"]["predictions_per_s"])
+
     res = {
         "metric": "bootstrappings/sec (n=630,N=1024) + encrypted predictions/sec; p99 latency",
         "value": round(pbs_per_s, 2), "unit": "bootstrappings/sec",
@@ -202,6 +325,8 @@ def main():
         "decrypt_ok_fraction": decrypt_ok,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_vs_unbatched": round(pbs_per_s / extra["unbatched"]["pbs_per_s"], 1),
+        "predictions": extra,
     }
     print(json.dumps(res), flush=True)
 
