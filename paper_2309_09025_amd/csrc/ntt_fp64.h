@@ -76,18 +76,31 @@ struct NttShape {
   static constexpr int LDS_DOUBLES = N + N / 16;
 };
 
-// Block-level barrier between the LDS write and read halves of an
-// exchange (TP threads of the polynomial may span several waves).
-__device__ __forceinline__ void poly_sync() { __syncthreads(); }
+// Ordering of the LDS accesses of one polynomial's threads.  When the TP
+// threads form a single wavefront, its LDS instructions execute in issue
+// order, so a wavefront-scope fence (which only stops the compiler from
+// moving accesses across it) is enough and no barrier or wait is spent;
+// polynomials spread over several waves need a workgroup barrier.
+template <int TP>
+__device__ __forceinline__ void poly_sync() {
+  if constexpr (TP <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 template <int LOGN, int LO_FROM, int LO_TO>
 __device__ __forceinline__ void exchange(double x[16], double* lds, int t) {
+  constexpr int TP = (1 << LOGN) / 16;
 #pragma unroll
   for (int r = 0; r < 16; ++r) lds[lds_slot(jmap<LOGN, LO_FROM>(t, r))] = x[r];
-  poly_sync();
+  poly_sync<TP>();
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = lds[lds_slot(jmap<LOGN, LO_TO>(t, r))];
-  poly_sync();
+  poly_sync<TP>();
 }
 
 template <int N>

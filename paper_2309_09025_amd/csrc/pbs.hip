@@ -113,7 +113,7 @@ blind_rotate_kernel(BrArgs a) {
       acc[1][j] = val;
     }
   }
-  __syncthreads();
+  poly_sync<TP>();
 
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t abar = (ct[i] + (1u << (31 - NU))) >> (32 - NU);
@@ -200,7 +200,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][t + TP * r] += upd[r];
     }
-    __syncthreads();
+    poly_sync<TP>();
   }
 
   if constexpr (!KS) {
