@@ -39,6 +39,49 @@
 
 namespace fs {
 
+// Pointer into global memory.  Pointers read from memory are generic to the
+// compiler, which then addresses through the flat aperture; a global one
+// lets it use a scalar base with 32-bit per-lane offsets.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+// Element i (i * sizeof(T) < 2^32) of a global array: the byte offset is
+// formed in 32 bits so the load takes the base from scalar registers and
+// one 32-bit offset register per lane.
+template <class T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t i) {
+  using gchar = const __attribute__((address_space(1))) char*;
+  return *(gptr<T>)((gchar)as_global(base) + i * (uint32_t)sizeof(T));
+}
+
+// A read-only table of doubles addressed through a raw buffer descriptor:
+// the descriptor lives in scalar registers and a load takes a per-lane
+// 32-bit byte offset plus a uniform one, so a group of loads whose offsets
+// differ by constants shares one vector register however far apart the
+// constants are.  (Word 3 = 0x00020000 is the gfx9 raw-buffer format: 32-bit
+// data, no swizzle; the range is left open, every offset used is < 2^31.)
+struct Tab {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ explicit Tab(const double* p)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, 0x7fffffff, 0x00020000)) {}
+  // element at byte offset vbytes + sbytes
+  __device__ double at(uint32_t vbytes, uint32_t sbytes) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vbytes, sbytes, 0));
+  }
+  // two adjacent elements in one 16-byte load
+  __device__ void at2(uint32_t vbytes, uint32_t sbytes, double& lo, double& hi) const {
+    struct D2 {
+      double lo, hi;
+    };
+    const D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, vbytes, sbytes, 0));
+    lo = v.lo;
+    hi = v.hi;
+  }
+};
+
 constexpr uint64_t kNttPrime = 0x6000000100001ull;  // 3*2^49 + 2^20 + 1
 constexpr double kP = 1688849861312513.0;
 constexpr double kPinv = 1.0 / 1688849861312513.0;
@@ -66,6 +109,20 @@ __device__ __forceinline__ int jmap(int t, int r) {
 // LDS slot of coefficient index j (one padding word per 16 keeps the three
 // register mappings free of bank conflicts beyond the minimum two passes).
 __device__ __forceinline__ int lds_slot(int j) { return j + (j >> 4); }
+
+// The slot of j(t, r) splits as slot(j(t, 0)) + slot(j(0, r)): the thread and
+// register parts of the index occupy disjoint bits, and their bits below 4
+// (thread bits under LO, register bits from LO up) never carry into bit 4.
+// So an exchange addresses LDS from one per-thread base with compile-time
+// offsets for the sixteen registers.
+template <int LOGN, int LO>
+__device__ __forceinline__ int slot_base(int t) {
+  return lds_slot(jmap<LOGN, LO>(t, 0));
+}
+template <int LO>
+__host__ __device__ constexpr int slot_reg(int r) {
+  return (r << LO) + ((r << LO) >> 4);
+}
 
 template <int LOGN>
 struct NttShape {
@@ -95,11 +152,13 @@ __device__ __forceinline__ void poly_sync() {
 template <int LOGN, int LO_FROM, int LO_TO>
 __device__ __forceinline__ void exchange(double x[16], double* lds, int t) {
   constexpr int TP = (1 << LOGN) / 16;
+  double* wp = lds + slot_base<LOGN, LO_FROM>(t);
+  const double* rp = lds + slot_base<LOGN, LO_TO>(t);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) lds[lds_slot(jmap<LOGN, LO_FROM>(t, r))] = x[r];
+  for (int r = 0; r < 16; ++r) wp[slot_reg<LO_FROM>(r)] = x[r];
   poly_sync<TP>();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = lds[lds_slot(jmap<LOGN, LO_TO>(t, r))];
+  for (int r = 0; r < 16; ++r) x[r] = rp[slot_reg<LO_TO>(r)];
   poly_sync<TP>();
 }
 
@@ -123,7 +182,7 @@ __device__ __forceinline__ void fwd_stages(double x[16], const double* __restric
       if (r & (1 << b)) continue;
       const int r2 = r | (1 << b);
       const int j = jmap<LOGN, LO>(t, r);
-      const double w = tw[(N >> (s + 1)) + (j >> (s + 1))];
+      const double w = ldg(tw, (N >> (s + 1)) + (j >> (s + 1)));
       const double m = mulmod(x[r2], w);
       x[r2] = x[r] - m;
       x[r] = x[r] + m;
@@ -148,55 +207,10 @@ __device__ __forceinline__ void ntt_fwd(double x[16], double* lds, const double*
   reduce16<S::N>(x);
 }
 
-// Inverse stages SLO up to SHI (decimation in time), register bits at LO.
-// Stage s pairs positions i and i + 2^s (i with bit s clear); the root is
-// omega^{-e}, e = (i mod 2^s) * N / 2^{s+1}; itw holds omega^{-e} at e.
-template <int LOGN, int LO, int SLO, int SHI>
-__device__ __forceinline__ void inv_stages(double x[16], const double* __restrict__ itw, int t) {
-  constexpr int N = 1 << LOGN;
-#pragma unroll
-  for (int s = SLO; s <= SHI; ++s) {
-    const int b = s - LO;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      if (r & (1 << b)) continue;
-      const int r2 = r | (1 << b);
-      const int i = jmap<LOGN, LO>(t, r);
-      const int e = (i & ((1 << s) - 1)) * (N >> (s + 1));
-      double m;
-      if (LO == 0 && (r & ((1 << s) - 1)) == 0) m = x[r2];  // omega^0 = 1
-      else m = mulmod(x[r2], itw[e]);
-      x[r2] = x[r] - m;
-      x[r] = x[r] + m;
-    }
-  }
-}
-
-// Inverse negacyclic NTT.  In: round-C mapping (bit-reversed positions),
-// |x| < 5 P.  Out: round-A mapping (thread t, register r holds coefficient
-// t + TP r), the exact centred residue of the coefficient.
-template <int LOGN>
-__device__ __forceinline__ void ntt_inv(double x[16], double* lds, const double* __restrict__ itw,
-                                        const double* __restrict__ post, int t) {
-  using S = NttShape<LOGN>;
-  reduce16<S::N>(x);
-  inv_stages<LOGN, 0, 0, 1>(x, itw, t);  // trivial roots double the bound: < 2.1 P
-  reduce16<S::N>(x);
-  inv_stages<LOGN, 0, 2, 3>(x, itw, t);  // < 2.3 P
-  reduce16<S::N>(x);
-  exchange<LOGN, 0, S::LOB>(x, lds, t);
-  inv_stages<LOGN, S::LOB, 4, LOGN - 5>(x, itw, t);  // < 3.1 P
-  reduce16<S::N>(x);
-  exchange<LOGN, S::LOB, S::LOA>(x, lds, t);
-  inv_stages<LOGN, S::LOA, LOGN - 4, LOGN - 1>(x, itw, t);  // < 4.4 P
-#pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = redc(mulmod(x[r], post[t + S::TP * r]));
-}
-
 // ---------------------------------------------------------------------------
-// Register-twiddle forms used by the blind rotation.  The same transforms as
-// ntt_fwd / ntt_inv, but every root comes from registers instead of a table
-// load inside the loop:
+// Register-twiddle forms used by the blind rotation (and the product
+// check).  The forward transform is that of ntt_fwd; every root comes from
+// registers instead of a table load inside a stage:
 //  - forward round A and inverse round C' use roots that are the same for
 //    all threads (they depend on register bits only); they are passed in the
 //    kernel-argument segment and read as scalars;
@@ -252,17 +266,16 @@ struct UniTw {
 };
 
 template <int LOGN, int LO, int SHI, int SLO>
-__device__ __forceinline__ void load_fwd_lane(double* w, const double* __restrict__ tw, int t) {
+__device__ __forceinline__ void load_fwd_lane(double* w, const Tab& tw, int t) {
   constexpr int N = 1 << LOGN;
 #pragma unroll
   for (int s = SHI; s >= SLO; --s) {
     const int b = s - LO;
+    // j(t, q 2^{b+1}) = j(t, 0) + q 2^{s+1}, so the root index is affine in q
+    const uint32_t base = (uint32_t)jmap<LOGN, LO>(t, 0) >> (s + 1);
 #pragma unroll
-    for (int q = 0; q < (16 >> (b + 1)); ++q) {
-      const int j = jmap<LOGN, LO>(t, q << (b + 1));
-      w[fwd_lane_off(LO, SHI, s) + q] =
-          tw[(N >> (s + 1)) + (j >> (s + 1))];
-    }
+    for (int q = 0; q < (16 >> (b + 1)); ++q)
+      w[fwd_lane_off(LO, SHI, s) + q] = tw.at(base * 8u, ((N >> (s + 1)) + q) * 8u);
   }
 }
 
@@ -310,7 +323,7 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
 // roots of rounds B and C are requested one round ahead.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
-                                            const double* __restrict__ tw, int t) {
+                                            const Tab& tw, int t) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
@@ -330,36 +343,19 @@ __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const Uni
   fwd_stages_reg<LOGN, 0, 3, LOGN - 10, 0>(x, wc);
 }
 
-template <int LOGN>
-__device__ __forceinline__ void load_fwd_tw(double* wf, const double* __restrict__ tw, int t) {
-  using S = NttShape<LOGN>;
-  load_fwd_lane<LOGN, S::LOB, LOGN - 5, 4>(wf, tw, t);
-  load_fwd_lane<LOGN, 0, 3, 0>(wf + RegTw<LOGN>::FB, tw, t);
-}
-
 template <int LOGN, int LO, int SLO, int SHI>
-__device__ __forceinline__ void load_inv_lane(double* w, const double* __restrict__ itw, int t) {
+__device__ __forceinline__ void load_inv_lane(double* w, const Tab& itw, int t) {
   constexpr int N = 1 << LOGN;
 #pragma unroll
   for (int s = SLO; s <= SHI; ++s) {
     const int b = s - LO;
+    // i(t, q) mod 2^s = (i(t, 0) mod 2^s) + q 2^LO for q < 2^b: affine in q
+    const uint32_t m = (uint32_t)N >> (s + 1);
+    const uint32_t base = ((uint32_t)jmap<LOGN, LO>(t, 0) & ((1u << s) - 1)) * m;
 #pragma unroll
-    for (int q = 0; q < (1 << b); ++q) {
-      const int i = jmap<LOGN, LO>(t, q);
-      w[inv_lane_off(LO, SLO, s) + q] = itw[(i & ((1 << s) - 1)) * (N >> (s + 1))];
-    }
+    for (int q = 0; q < (1 << b); ++q)
+      w[inv_lane_off(LO, SLO, s) + q] = itw.at(base * 8u, ((uint32_t)q << LO) * m * 8u);
   }
-}
-
-template <int LOGN>
-__device__ __forceinline__ void load_inv_tw(double* wi, const double* __restrict__ itw,
-                                            const double* __restrict__ post, int t) {
-  using S = NttShape<LOGN>;
-  using R = RegTw<LOGN>;
-  load_inv_lane<LOGN, S::LOB, 4, LOGN - 5>(wi, itw, t);
-  load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wi + R::IB, itw, t);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) wi[R::IB + R::IA + r] = post[t + S::TP * r];
 }
 
 // Inverse stages SLO up to SHI of the round whose first stage is RLO.
@@ -396,15 +392,18 @@ __device__ __forceinline__ void inv_roundC_uni(double x[16], const UniTw& u, int
   }
 }
 
-// Inverse transform with register roots: the transform of ntt_inv with
-// reductions before stages 0, 3 and 7 only (stages 0..2 contain butterflies
-// whose root is 1 and double the bound); ends with the twist psi^-j N^-1 and
-// a reduction, giving the exact centred residue.  The per-thread roots of
-// each round are requested one round ahead.
+// Inverse negacyclic transform with register roots.  In: round-C mapping
+// (bit-reversed positions), |x| < 5 P.  Decimation in time on the
+// bit-reversed order with roots omega^-1 = psi^-2: stage s pairs positions
+// i and i + 2^s (bit s of i clear) with root omega^{-e}, e = (i mod 2^s)
+// N / 2^{s+1}.  Reductions before stages 0, 3 and 7 only (stages 0..2 contain
+// butterflies whose root is 1 and double the bound); ends with the twist
+// psi^-j N^-1 and a reduction, giving the exact centred residue in round-A
+// mapping (thread t, register r: coefficient t + TP r).  The per-thread roots
+// of each round are requested one round ahead.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const UniTw& u,
-                                            const double* __restrict__ itw,
-                                            const double* __restrict__ post, int t) {
+                                            const Tab& itw, const Tab& post, int t) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B': stages 4..BHI, round A': BHI+1..LOGN-1
@@ -421,7 +420,7 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
   exchange<LOGN, S::LOB, S::LOA>(x, lds, t);
   double wp[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) wp[r] = post[t + S::TP * r];
+  for (int r = 0; r < 16; ++r) wp[r] = post.at((uint32_t)t * 8u, (uint32_t)(S::TP * r) * 8u);
   if constexpr (LOGN - 4 <= 6) {  // N = 1024: stage 6 is the first of round A'
     inv_stages_reg<LOGN, S::LOA, LOGN - 4, LOGN - 4, 6>(x, wa);
     reduce16<S::N>(x);
@@ -440,13 +439,6 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
 __device__ __forceinline__ uint32_t low32_magic(double e) {
   const double y = e + 6755399441055744.0;  // 1.5 * 2^52
   return (uint32_t)__double_as_longlong(y);
-}
-
-// Low 32 bits of an integer-valued double of magnitude < 2^52.
-__device__ __forceinline__ uint32_t low32(double e) {
-  const double hi = __builtin_floor(e * 0x1p-32);
-  const double lo = __builtin_fma(-hi, 0x1p32, e);  // in [0, 2^32)
-  return (uint32_t)lo;
 }
 
 }  // namespace fs

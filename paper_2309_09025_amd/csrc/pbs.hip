@@ -59,15 +59,17 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // Initialization ACC = (0, X^{-b~} v) and sample extraction of
 // coefficient 0 are fused at both ends.
 //
-// Latency: the key slice of a digit row is requested before that row's
-// forward transform and consumed after it; the roots shared by all threads
-// come from the kernel-argument segment and the per-thread ones are loaded
-// once per step (forward) or per inverse phase, never inside a transform.
-template <int LOGN, int L, int BG, int LIMBS, bool PREF, int WPE, bool KS>
+// Latency: the key slice of a digit row (16 registers x 2*limbs values per
+// thread) is requested at a point set by PF and consumed after the row's
+// forward transform: PF = 0 after the transform, in two halves; 1 first half
+// before the transform, second after it; 2 the whole slice before.  The
+// roots shared by all threads come from the kernel-argument segment and the
+// per-thread ones are requested one round ahead.  WPE is the number of
+// waves per SIMD the register allocation must allow.
+template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, bool KS>
 __global__ void __launch_bounds__(NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
-  using R = RegTw<LOGN>;
   constexpr int N = S::N, TP = S::TP, ROWS = 2 * L;
   constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr uint32_t NU = LOGN + 1;  // log2(2N)
@@ -80,7 +82,7 @@ blind_rotate_kernel(BrArgs a) {
   const uint32_t n = a.n;
   const uint64_t g = job / a.nlut;  // ciphertext of this job
   const uint32_t* ct;
-  const double* __restrict__ bsk;
+  const double* bsk;
   if (a.ranges) {  // multi-key launch: the range of g gives input and key
     const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
     ct = rg.in + (g - rg.first) * (size_t)(n + 1);
@@ -89,6 +91,7 @@ blind_rotate_kernel(BrArgs a) {
     ct = a.in + g * (size_t)(n + 1);
     bsk = a.bsk;
   }
+  const Tab key(bsk), fwd_tw(a.fwd_tw), inv_tw(a.inv_tw), post(a.post);
   const uint32_t* v = (job % a.nlut) == 0 ? a.tpoly0 : a.tpoly1;
 
   // gadget rounding offset: sum_{j=1..L} (Bg/2) 2^{32 - j BG} + 2^{31 - L BG}
@@ -118,67 +121,69 @@ blind_rotate_kernel(BrArgs a) {
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t abar = (ct[i] + (1u << (31 - NU))) >> (32 - NU);
     if (abar == 0) continue;  // X^0 ACC - ACC = 0: every digit is zero
-    double p0[LIMBS][16], p1[LIMBS][16];
+    double p0[LIMBS][16], p1[LIMBS][16], xd[16];
 #pragma unroll
     for (int lb = 0; lb < LIMBS; ++lb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) { p0[lb][r] = 0.0; p1[lb][r] = 0.0; }
 
-    const double* bsk_i = bsk + (size_t)i * ROWS * 16 * TP * G;
+    // byte offset of step i's key slice (< 2^31: n * 2l * 16 * TP * G * 8)
+    const uint32_t key_i = i * (uint32_t)(ROWS * 16 * TP * G * 8);
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
+      // D_c = X^{a~} ACC_c - ACC_c plus the gadget offset.  Coefficient j of
+      // X^{a~} ACC is ACC[k mod N] with k = j - a~ in (-2N, N), negated when
+      // k mod 2N >= N (one wrap past X^N = -1).
       uint32_t d[16];
+      const uint32_t* ac = acc[c];
+      const int kb = t - (int)abar;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int j = t + TP * r;
-        int src = j - (int)abar;
-        uint32_t rot;
-        if (src >= 0) rot = acc[c][src];
-        else if (src + N >= 0) rot = 0u - acc[c][src + N];
-        else rot = acc[c][src + 2 * N];
-        d[r] = rot - acc[c][j] + off;
+        const int k = kb + TP * r;
+        const uint32_t v = ac[k & (N - 1)];
+        const uint32_t neg = 0u - (((uint32_t)k >> LOGN) & 1u);
+        d[r] = ((v ^ neg) - neg) - ac[t + TP * r] + off;
       }
 #pragma unroll 1
       for (int lv = 0; lv < L; ++lv) {
-        // request this digit row's key slice before the transform (PREF) or
-        // after it, in two halves (fewer live registers)
-        const double* row = bsk_i + (size_t)(c * L + lv) * 16 * TP * G;
+        const uint32_t row = key_i + (uint32_t)((c * L + lv) * 16 * TP * G * 8);
         double g[16][G];
-        if (PREF) {
+        auto load_half = [&](int h) __attribute__((always_inline)) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r)
+          for (int r = 8 * h; r < 8 * h + 8; ++r)
 #pragma unroll
-            for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
-        }
+            for (int q = 0; q < G; q += 2)
+              key.at2((uint32_t)t * (G * 8), row + (uint32_t)((r * TP * G + q) * 8), g[r][q],
+                      g[r][q + 1]);
+        };
+        auto mac_half = [&](int h) __attribute__((always_inline)) {
+#pragma unroll
+          for (int r = 8 * h; r < 8 * h + 8; ++r)
+#pragma unroll
+            for (int lb = 0; lb < LIMBS; ++lb) {
+              p0[lb][r] += mulmod(xd[r], g[r][lb]);
+              p1[lb][r] += mulmod(xd[r], g[r][LIMBS + lb]);
+            }
+        };
+        if constexpr (PF >= 1) load_half(0);
+        if constexpr (PF == 2) load_half(1);
         const uint32_t sh = 32 - (lv + 1) * BG;
-        double x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          x[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
-        ntt_fwd_reg<LOGN>(x, lds, a.uni, a.fwd_tw, t);
-        if (!PREF) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-#pragma unroll
-            for (int r = 8 * h; r < 8 * h + 8; ++r)
-#pragma unroll
-              for (int q = 0; q < G; ++q) g[r][q] = row[((size_t)r * TP + t) * G + q];
-#pragma unroll
-            for (int r = 8 * h; r < 8 * h + 8; ++r)
-#pragma unroll
-              for (int lb = 0; lb < LIMBS; ++lb) {
-                p0[lb][r] += mulmod(x[r], g[r][lb]);
-                p1[lb][r] += mulmod(x[r], g[r][LIMBS + lb]);
-              }
-          }
+          xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+        ntt_fwd_reg<LOGN>(xd, lds, a.uni, fwd_tw, t);
+        if constexpr (PF == 0) {
+          load_half(0);
+          mac_half(0);
+          load_half(1);
+          mac_half(1);
+        } else if constexpr (PF == 1) {
+          load_half(1);
+          mac_half(0);
+          mac_half(1);
         } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-#pragma unroll
-          for (int lb = 0; lb < LIMBS; ++lb) {
-            p0[lb][r] += mulmod(x[r], g[r][lb]);
-            p1[lb][r] += mulmod(x[r], g[r][LIMBS + lb]);
-          }
+          mac_half(0);
+          mac_half(1);
         }
       }
     }
@@ -190,7 +195,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int lb = 0; lb < LIMBS; ++lb) {
         double* y = c == 0 ? p0[lb] : p1[lb];
-        ntt_inv_reg<LOGN>(y, lds, a.uni, a.inv_tw, a.post, t);
+        ntt_inv_reg<LOGN>(y, lds, a.uni, inv_tw, post, t);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t part = low32_magic(y[r]);
@@ -388,7 +393,7 @@ polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, ui
     double x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = (double)d[(size_t)q * S::N + t + S::TP * r];
-    ntt_fwd_reg<LOGN>(x, lds, uni, tw, t);
+    ntt_fwd_reg<LOGN>(x, lds, uni, Tab(tw), t);
 #pragma unroll
     for (int lb = 0; lb < LIMBS; ++lb) {
       double y[16];
@@ -414,7 +419,7 @@ polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, ui
   uint32_t res[16];
 #pragma unroll
   for (int lb = 0; lb < LIMBS; ++lb) {
-    ntt_inv_reg<LOGN>(accv[lb], lds, uni, itw, post, t);
+    ntt_inv_reg<LOGN>(accv[lb], lds, uni, Tab(itw), Tab(post), t);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const uint32_t part = low32_magic(accv[lb][r]);
@@ -450,9 +455,10 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
   return 0;
 }
 
-// Kernel variants the tuner chooses from: (key-slice prefetch, minimum waves
-// per SIMD the register allocation must allow).  N = 1024: 0 = (after, 2),
-// 1 = (before, 1), 2 = (after, 3), 3 = (after, 1).
+// Kernel variants the tuner chooses from: (PF key-slice prefetch point,
+// minimum waves per SIMD the register allocation must allow).
+// N = 1024: (0, 2), (1, 2), (2, 1), (2, 2); N = 2048: (0, 1), (2, 1), (1, 1),
+// (0, 2).
 int blind_rotate_variants() { return 4; }
 
 template <bool KS>
@@ -460,18 +466,18 @@ static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipS
   const dim3 g((uint32_t)jobs);
   if (N == 1024) {
     switch (variant) {
-      case 0: blind_rotate_kernel<10, 3, 7, 1, false, 2, KS><<<g, 64, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<10, 3, 7, 1, true, 1, KS><<<g, 64, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<10, 3, 7, 1, false, 3, KS><<<g, 64, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<10, 3, 7, 1, false, 1, KS><<<g, 64, 0, st>>>(a); break;
+      case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, KS><<<g, 64, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS><<<g, 64, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, KS><<<g, 64, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, KS><<<g, 64, 0, st>>>(a); break;
       default: return -2;
     }
   } else if (N == 2048) {
     switch (variant) {
-      case 0: blind_rotate_kernel<11, 2, 10, 2, false, 1, KS><<<g, 128, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<11, 2, 10, 2, true, 1, KS><<<g, 128, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<11, 2, 10, 2, true, 2, KS><<<g, 128, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<11, 2, 10, 2, false, 2, KS><<<g, 128, 0, st>>>(a); break;
+      case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS><<<g, 128, 0, st>>>(a); break;
+      case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, KS><<<g, 128, 0, st>>>(a); break;
+      case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, KS><<<g, 128, 0, st>>>(a); break;
+      case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, KS><<<g, 128, 0, st>>>(a); break;
       default: return -2;
     }
   } else {

@@ -79,6 +79,22 @@ def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     assert np.array_equal(got, O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
 
 
+@pytest.mark.parametrize("variant", range(4))
+def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, variant):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(1)
+    m, ct = _pbs_inputs(P, sk, okeys_b, 2, first=600 + 2 * variant)
+    f = O.lut_fire(P.p, 4)
+    out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
+    ctx.set_br_variant(P.N, variant)
+    try:
+        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
+        got = _host(out)
+    finally:
+        ctx.set_br_variant(P.N, 0)
+    assert np.array_equal(got, O.pbs(okeys_b, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
+
+
 def test_pbs_lif_bit_exact(gpu_env, okeys_a):
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
