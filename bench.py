@@ -320,7 +320,7 @@ def main():
                                f"N={P.N} k=1 l={P.l} Bg=2^{P.bg_bit}, KS base 2^{P.ks_base_bit} t={P.ks_t}",
                    "batch": B, "n": P.n, "N": P.N, "l": P.l, "bg_bit": P.bg_bit, "p": P.p},
         "breakdown_ms": {"blind_rotate_kernel": round(br_avg, 4),
-                         "keyswitch_batched_kernel": round(sum(ks_ms) / len(ks_ms), 4)},
+                         "key_switch (ks_body_kernel + keyswitch_mfma_kernel)": round(sum(ks_ms) / len(ks_ms), 4)},
         "fs_pbs_matches_step": bool(np.array_equal(F.to_host(d_ks), out)),
         "decrypt_ok_fraction": decrypt_ok,
         "roofline": roofline,

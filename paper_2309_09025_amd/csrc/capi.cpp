@@ -23,6 +23,7 @@ struct fs_devkey {
   int device = 0;
   double* bsk = nullptr;    // NTT domain, see launch_bsk_to_ntt
   uint32_t* ksk = nullptr;  // [N][t][base-1][n+1]
+  int8_t* kskp = nullptr;   // the KSK as byte planes for the matrix-core key switch
   double* fwd_tw = nullptr;
   double* inv_tw = nullptr;
   double* post = nullptr;
@@ -251,6 +252,7 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   KsArgs ks{};
   ks.in = br.ext;
   ks.ksk = dk->ksk;
+  ks.kskp = dk->kskp;
   ks.out0 = out0;
   ks.out1 = out1;
   ks.plain_add[0] = plain_add[0];
@@ -452,6 +454,9 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   // the KSK is followed by one all-zero row (digit value 0 in the fused key switch)
   e = hipMalloc(&dk->ksk, (evk->ksk.size() + P.n + 1) * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
+  const size_t planes = fs::ksk_planes_bytes(P.N, P.n);
+  e = hipMalloc(&dk->kskp, planes);
+  if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK plane allocation failed"));
   e = hipMalloc(&coef, bsk_words * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: staging allocation failed"));
   rc = upload_tables(P.N, &dk->fwd_tw, &dk->inv_tw, &dk->post, &dk->uni);
@@ -466,11 +471,13 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
                  "BSK conversion");
   if (rc) return cleanup(rc);
+  rc = launch_rc(launch_ksk_to_planes(P.N, P.n, dk->ksk, dk->kskp, nullptr), "KSK conversion");
+  if (rc) return cleanup(rc);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: conversion"));
   (void)hipFree(coef);
   coef = nullptr;
-  dk->bytes = bsk_ntt * sizeof(double) + evk->ksk.size() * sizeof(uint32_t) +
+  dk->bytes = bsk_ntt * sizeof(double) + evk->ksk.size() * sizeof(uint32_t) + planes +
               (size_t)(5 * P.N / 2) * sizeof(double);
   *dk_out = dk;
   return FS_OK;
@@ -489,6 +496,7 @@ void fs_devkey_free(fs_devkey* dk) {
   DeviceGuard g(dk->device);
   if (dk->bsk) (void)hipFree(dk->bsk);
   if (dk->ksk) (void)hipFree(dk->ksk);
+  if (dk->kskp) (void)hipFree(dk->kskp);
   if (dk->fwd_tw) (void)hipFree(dk->fwd_tw);  // one allocation holds all three tables
   delete dk;
 }
@@ -644,6 +652,7 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
     KsArgs ks{};
     ks.in = ctx->ext + (size_t)(2 * first) * (P.N + 1);
     ks.ksk = key->ksk;
+    ks.kskp = key->kskp;
     ks.plain_add[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
     ks.plain_add[1] = 0u;
     ks.nlut = 2;
@@ -670,6 +679,7 @@ int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B,
   KsArgs ks{};
   ks.in = in;
   ks.ksk = dk->ksk;
+  ks.kskp = dk->kskp;
   ks.out0 = out;
   ks.out1 = nullptr;
   ks.nlut = 1;

@@ -57,6 +57,9 @@ struct BrArgs {
 struct KsArgs {
   const uint32_t* in;  // [jobs][N+1]
   const uint32_t* ksk; // [N][t][base-1][n+1]
+  // the same key as signed byte planes in matrix-core operand order (t = 8,
+  // base 4; see launch_ksk_to_planes), or null
+  const int8_t* kskp;
   uint32_t* out0;      // program function 0 outputs, [jobs/nlut][n+1]
   uint32_t* out1;      // program function 1 outputs (nlut == 2)
   uint32_t plain_add[2];  // Delta * c added to b per program function
@@ -73,6 +76,12 @@ int blind_rotate_variants();
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool fused_ks,
                         hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
+// words per KSK row n+1 rounded up to the 32-word tiles of the matrix-core
+// key switch, and the byte size of its plane layout
+uint32_t ks_word_tiles(uint32_t n);
+size_t ksk_planes_bytes(uint32_t N, uint32_t n);
+int launch_ksk_to_planes(uint32_t N, uint32_t n, const uint32_t* ksk, int8_t* planes,
+                         hipStream_t st);
 int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, uint32_t* out,
                    const double* tw, const double* itw, const double* post, const UniTw& uni,
                    hipStream_t st);

@@ -269,9 +269,27 @@ blind_rotate_kernel(BrArgs a) {
 // output word w of one sample.  out = (0, b') - sum over coefficients i and
 // digits j of KSK[i][j][d_ij - 1] (d_ij != 0), where a'_i is rounded to
 // t*beta bits and split into base-2^beta digits, most significant first.
-// Sample m is job (ciphertext m / nlut, program function m % nlut); its
-// result goes to out[m % nlut] at row m / nlut, and plain_add[m % nlut] is
-// added to b (FHE-Fire adds Delta * 1 after bootstrapping).
+// Sample m is job job0 + m (ciphertext (job0 + m) / nlut, program function
+// (job0 + m) % nlut); its result goes to that function's output at the
+// ciphertext's row (or its range's row in a multi-key launch), and the
+// function's plain_add is added to b (FHE-Fire adds Delta * 1 after
+// bootstrapping).
+// program function and output row of key-switch sample m (nlut is 1 or 2)
+__device__ __forceinline__ uint32_t ks_lut(const KsArgs& a, size_t m) {
+  return a.nlut == 2 ? (uint32_t)((a.job0 + m) & 1u) : 0u;
+}
+__device__ __forceinline__ uint32_t* ks_output_row(const KsArgs& a, size_t m) {
+  const uint64_t job = a.job0 + m;
+  const uint64_t g = a.nlut == 2 ? job >> 1 : job;
+  const uint32_t lut = a.nlut == 2 ? (uint32_t)(job & 1u) : 0u;
+  const size_t w1 = a.n + 1;
+  if (a.ranges) {
+    const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+    return (lut == 0 ? rg.out0 : rg.out1) + (g - rg.first) * w1;
+  }
+  return (lut == 0 ? a.out0 : a.out1) + g * w1;
+}
+
 __global__ void __launch_bounds__(256)
 keyswitch_kernel(KsArgs a) {
   const uint32_t w = blockIdx.y * 256 + threadIdx.x;
@@ -280,7 +298,7 @@ keyswitch_kernel(KsArgs a) {
   const uint32_t prec = t * beta;
   if (w > n) return;
   const uint32_t* in = a.in + m * (size_t)(N + 1);
-  const uint32_t lut = (uint32_t)(m % a.nlut);
+  const uint32_t lut = ks_lut(a, m);
   uint32_t r = w == n ? in[N] + a.plain_add[lut] : 0u;
   const size_t stride = (size_t)(n + 1);
   const uint32_t* ksk = a.ksk + w;
@@ -292,84 +310,158 @@ keyswitch_kernel(KsArgs a) {
       if (dg) r -= rows[((size_t)j * base1 + (dg - 1)) * stride];
     }
   }
-  uint32_t* out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * stride;
-  out[w] = r;
+  ks_output_row(a, m)[w] = r;
 }
 
 // ---------------------------------------------------------------------------
-// Batched key switching (t = 8 digits of base 4).  A block serves KC = 16
-// samples and a 256-word slice of the output: every KSK row word a thread
-// loads is used by all 16 samples.  Digits of all 16 samples for position
-// (i, j) are packed two bits each into one word in LDS; per (i, j) a thread
-// loads the three candidate rows and each sample subtracts the one its
-// digit selects (the digit is the same for every thread, so the selection
-// costs no divergence).  Output routing and the +Delta epilogue are those of
-// keyswitch_kernel.
-constexpr int KC = 16;
+// Key switching of a batch on the matrix cores (t = 8 digits of base 4).
+//
+// For sample s the key switch subtracts, for every coefficient i and digit
+// position j, the KSK row selected by the digit d_{s,i,j}.  Writing the
+// selection as a one-hot vector over the four digit values (value 0 selects
+// an all-zero row), the batch is the product
+//     out[s][w] = [w = n] b'_s - sum_k A[s][k] K[k][w],  k = (i, j, v),
+//     A[s][k] = [d_{s,i,j} = v],  K[(i,j,v)][w] = KSK[i][j][v-1][w] (0 if v = 0)
+// over the integers mod 2^32.  K is split into four signed bytes,
+// K = sum_b 256^b K_b with K_b in [-128, 128), so each A K_b is an exact
+// int8 x int8 -> int32 product (a sum of 8N terms of magnitude <= 128) on
+// v_mfma_i32_32x32x32_i8, and out = [w = n] b' - sum_b 256^b (A K_b) mod 2^32.
+//
+// Operand order of v_mfma_i32_32x32x32_i8 (32 x 32 x 32 tile): lane l holds
+// A[l % 32][16 (l / 32) + x] and B[16 (l / 32) + x][l % 32] in byte x of its
+// four registers; result C[i][j] sits in lane j + 32 ((i / 4) % 2), register
+// (i % 4) + 4 (i / 8).  The 32 k of a tile are one coefficient i: k = 4 j + v.
+// So lane l builds, for its sample, one word per digit position
+// j = 4 (l / 32) + q: the byte of value d set, 1 << 8 d.
+//
+// Plane layout (built once per key by ksk_to_planes_kernel): for coefficient
+// i, word tile wt and byte plane b, the 64 lanes' 16-byte B registers are
+// stored contiguously, [i][wt][b][lane][16].
+//
+// A wave computes MA fragments of 32 samples times one 32-word tile times
+// the four planes (4 MA accumulator tiles); every B register it loads is
+// used by MA products.
+typedef int fs_v4i __attribute__((ext_vector_type(4)));
+typedef int fs_v16i __attribute__((ext_vector_type(16)));
 
-template <int N>
+uint32_t ks_word_tiles(uint32_t n) { return (n + 1 + 31) / 32; }
+size_t ksk_planes_bytes(uint32_t N, uint32_t n) {
+  return (size_t)N * ks_word_tiles(n) * 4 * 64 * 16;
+}
+
+__device__ __forceinline__ int8_t signed_byte_plane(uint32_t u, int b) {
+  // u = sum_b 256^b s_b (mod 2^32) with s_b in [-128, 128)
+  int8_t sb = 0;
+#pragma unroll
+  for (int q = 0; q <= 3; ++q) {
+    sb = (int8_t)(u & 0xFFu);
+    if (q == b) break;
+    u = (u - (uint32_t)(int32_t)sb) >> 8;
+  }
+  return sb;
+}
+
+__global__ void __launch_bounds__(64)
+ksk_to_planes_kernel(const uint32_t* __restrict__ ksk, int8_t* __restrict__ planes, uint32_t n,
+                     uint32_t wtiles) {
+  const uint32_t l = threadIdx.x, i = blockIdx.x, wt = blockIdx.y;
+  const uint32_t w1 = n + 1, w = 32 * wt + (l & 31);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    int8_t bytes[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const uint32_t k = 16 * (l >> 5) + x, j = k >> 2, v = k & 3;
+      bytes[x] = (v == 0 || w >= w1)
+                     ? (int8_t)0
+                     : signed_byte_plane(ksk[(((size_t)i * 8 + j) * 3 + (v - 1)) * w1 + w], b);
+    }
+    int8_t* dst = planes + ((((size_t)i * wtiles + wt) * 4 + b) * 64 + l) * 16;
+#pragma unroll
+    for (int x = 0; x < 16; ++x) dst[x] = bytes[x];
+  }
+}
+
+// (0, b' + plain_add) in every output row of the batch; the matrix-core
+// kernels then subtract their partial sums atomically (integer addition
+// mod 2^32 is exact in any order).
 __global__ void __launch_bounds__(256)
-keyswitch_batched_kernel(KsArgs a, uint32_t count) {
-  constexpr int KT = 8, KB = 2, PREC = KT * KB;
-  __shared__ uint32_t dig[N * KT];
-  const uint32_t tid = threadIdx.x;
-  const size_t m0 = (size_t)blockIdx.x * KC;
+ks_body_kernel(KsArgs a, uint32_t count) {
+  const uint32_t m = blockIdx.x, w = blockIdx.y * 256 + threadIdx.x, n = a.n;
+  if (m >= count || w > n) return;
+  const uint32_t body =
+      w == n ? a.in[(size_t)m * (a.N + 1) + a.N] + a.plain_add[ks_lut(a, m)] : 0u;
+  ks_output_row(a, m)[w] = body;
+}
+
+// Grid: (sample groups of 32 MA, word tiles, K splits).  Split z covers
+// coefficients [z N / gridDim.z, (z + 1) N / gridDim.z).
+template <int N, int MA>
+__global__ void __launch_bounds__(64, 2)
+keyswitch_mfma_kernel(KsArgs a, uint32_t count) {
+  constexpr int PREC = 16;  // 8 digits of 2 bits
+  const uint32_t l = threadIdx.x, h = l >> 5, c32 = l & 31;
+  const uint32_t s0 = blockIdx.x * (32 * MA);
+  const uint32_t wt = blockIdx.y, wtiles = gridDim.y;
+  const uint32_t ibeg = blockIdx.z * (N / gridDim.z), iend = ibeg + N / gridDim.z;
   const uint32_t n = a.n, w1 = n + 1;
-  // digits of the KC samples, packed: bits 2c..2c+1 of dig[i*8 + j]
-  for (uint32_t i = tid; i < (uint32_t)N; i += 256) {
-    uint32_t words[KT];
+
+  fs_v16i acc[MA][4];
 #pragma unroll
-    for (int j = 0; j < KT; ++j) words[j] = 0u;
+  for (int f = 0; f < MA; ++f)
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      if (m0 + c < count) {
-        const uint32_t ai = a.in[(m0 + c) * (size_t)(N + 1) + i];
-        const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
+    for (int b = 0; b < 4; ++b) acc[f][b] = fs_v16i{};
+
+  // the sample each lane builds A rows for (padding samples read sample 0
+  // and are given digit 0, which selects the zero rows)
+  const uint32_t* row[MA];
+  bool live[MA];
 #pragma unroll
-        for (int j = 0; j < KT; ++j) words[j] |= ((abar >> ((KT - 1 - j) * KB)) & 3u) << (2 * c);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < KT; ++j) dig[i * KT + j] = words[j];
+  for (int f = 0; f < MA; ++f) {
+    const uint32_t s = s0 + 32 * f + c32;
+    live[f] = s < count;
+    row[f] = a.in + (size_t)(live[f] ? s : 0) * (N + 1);
   }
-  __syncthreads();
-  const uint32_t w = blockIdx.y * 256 + tid;
-  const uint32_t wc = w < w1 ? w : n;  // clamp the idle tail threads in bounds
-  uint32_t acc[KC];
+  const fs_v4i* __restrict__ bk =
+      reinterpret_cast<const fs_v4i*>(a.kskp) + (size_t)wt * 4 * 64 + l;
+  const size_t bstep = (size_t)wtiles * 4 * 64;  // fs_v4i per coefficient
+  const uint32_t shift = 8 - 8 * h;  // digits 4h .. 4h+3 of the rounded coefficient
+
+#pragma unroll 2
+  for (uint32_t i = ibeg; i < iend; ++i) {
+    const fs_v4i* bi = bk + (size_t)i * bstep;
+    fs_v4i bq[4];
 #pragma unroll
-  for (int c = 0; c < KC; ++c) acc[c] = 0u;
-  const uint32_t* __restrict__ ksk = a.ksk + wc;
-  for (int i = 0; i < N; ++i) {
+    for (int b = 0; b < 4; ++b) bq[b] = bi[b * 64];
 #pragma unroll
-    for (int j = 0; j < KT; ++j) {
-      const uint32_t dw = __builtin_amdgcn_readfirstlane(dig[i * KT + j]);
-      const uint32_t* rows = ksk + (size_t)((i * KT + j) * 3) * w1;
-      const uint32_t r1 = rows[0], r2 = rows[w1], r3 = rows[2 * w1];
+    for (int f = 0; f < MA; ++f) {
+      const uint32_t ai = live[f] ? row[f][i] : 0u;
+      const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
+      const uint32_t nib = (abar >> shift) & 0xFFu;
+      fs_v4i A;
+      A[0] = (int)(1u << (((nib >> 6) & 3u) << 3));
+      A[1] = (int)(1u << (((nib >> 4) & 3u) << 3));
+      A[2] = (int)(1u << (((nib >> 2) & 3u) << 3));
+      A[3] = (int)(1u << ((nib & 3u) << 3));
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        const uint32_t d = (dw >> (2 * c)) & 3u;
-        if (d) acc[c] -= d == 1 ? r1 : (d == 2 ? r2 : r3);
-      }
+      for (int b = 0; b < 4; ++b)
+        acc[f][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, bq[b], acc[f][b], 0, 0, 0);
     }
   }
+
+  // epilogue: combine the planes and subtract the partial sum
+  const uint32_t w = 32 * wt + c32;
   if (w >= w1) return;
 #pragma unroll
-  for (int c = 0; c < KC; ++c) {
-    const size_t m = m0 + c;
-    if (m >= count) break;
-    const uint32_t lut = (uint32_t)((a.job0 + m) % a.nlut);
-    const uint32_t* in = a.in + m * (size_t)(N + 1);
-    const uint32_t v = w == n ? acc[c] + in[N] + a.plain_add[lut] : acc[c];
-    const uint64_t g = (a.job0 + m) / a.nlut;
-    uint32_t* out;
-    if (a.ranges) {
-      const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
-      out = (lut == 0 ? rg.out0 : rg.out1) + (g - rg.first) * (size_t)w1;
-    } else {
-      out = (lut == 0 ? a.out0 : a.out1) + (m / a.nlut) * (size_t)w1;
+  for (int f = 0; f < MA; ++f)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t m = s0 + 32 * f + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (m >= count) continue;
+      const uint32_t sum = (uint32_t)acc[f][0][r] + ((uint32_t)acc[f][1][r] << 8) +
+                           ((uint32_t)acc[f][2][r] << 16) + ((uint32_t)acc[f][3][r] << 24);
+      atomicSub(ks_output_row(a, m) + w, sum);
     }
-    out[w] = v;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -496,15 +588,26 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, b
 
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {
   if (count == 0) return 0;
-  const bool batched = a.t == 8 && a.beta == 2 && (a.N == 1024 || a.N == 2048);
-  if (batched) {
-    dim3 g((uint32_t)((count + KC - 1) / KC), (a.n + 1 + 255) / 256);
-    if (a.N == 1024) keyswitch_batched_kernel<1024><<<g, 256, 0, st>>>(a, (uint32_t)count);
-    else keyswitch_batched_kernel<2048><<<g, 256, 0, st>>>(a, (uint32_t)count);
+  const bool mfma = a.kskp && a.t == 8 && a.beta == 2 && (a.N == 1024 || a.N == 2048);
+  if (mfma) {
+    constexpr int MA = 2, SPLIT = 4;
+    ks_body_kernel<<<dim3((uint32_t)count, (a.n + 1 + 255) / 256), 256, 0, st>>>(a, (uint32_t)count);
+    FS_LAUNCH_CHECK();
+    dim3 g((uint32_t)((count + 32 * MA - 1) / (32 * MA)), ks_word_tiles(a.n), SPLIT);
+    if (a.N == 1024) keyswitch_mfma_kernel<1024, MA><<<g, 64, 0, st>>>(a, (uint32_t)count);
+    else keyswitch_mfma_kernel<2048, MA><<<g, 64, 0, st>>>(a, (uint32_t)count);
   } else {
     dim3 g((uint32_t)count, (a.n + 1 + 255) / 256);
     keyswitch_kernel<<<g, 256, 0, st>>>(a);
   }
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_ksk_to_planes(uint32_t N, uint32_t n, const uint32_t* ksk, int8_t* planes,
+                         hipStream_t st) {
+  const uint32_t wtiles = ks_word_tiles(n);
+  ksk_to_planes_kernel<<<dim3(N, wtiles), 64, 0, st>>>(ksk, planes, n, wtiles);
   FS_LAUNCH_CHECK();
   return 0;
 }

@@ -121,14 +121,28 @@ def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
     assert np.array_equal(_host(vv), vnew)
 
 
-def test_keyswitch_bit_exact(gpu_env, okeys_a):
+@pytest.mark.parametrize("count", [1, 21, 64, 65, 200])
+def test_keyswitch_bit_exact(gpu_env, okeys_a, count):
+    """Ragged batch sizes around the 64-sample groups of the matrix-core
+    key switch (padding samples must not leak into real ones)."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
-    x = synth.rng(synth.SEED_DATA, 600).integers(0, 2 ** 32, size=(21, P.N + 1),
-                                                  dtype=np.uint64).astype(np.uint32)
-    out = torch.zeros((21, P.n + 1), dtype=torch.int32, device="cuda")
+    x = synth.rng(synth.SEED_DATA, 600 + count).integers(0, 2 ** 32, size=(count, P.N + 1),
+                                                          dtype=np.uint64).astype(np.uint32)
+    out = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
     F.keyswitch(ctx, dk, _dev(x), out)
     assert np.array_equal(_host(out), O.keyswitch(okeys_a, x))
+
+
+@pytest.mark.parametrize("count", [3, 70])
+def test_keyswitch_shape_b_bit_exact(gpu_env, okeys_b, count):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(1)
+    x = synth.rng(synth.SEED_DATA, 700 + count).integers(0, 2 ** 32, size=(count, P.N + 1),
+                                                          dtype=np.uint64).astype(np.uint32)
+    out = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
+    F.keyswitch(ctx, dk, _dev(x), out)
+    assert np.array_equal(_host(out), O.keyswitch(okeys_b, x))
 
 
 @pytest.mark.parametrize("O_,I", [(1, 1), (32, 64), (37, 129), (256, 300)])
