@@ -51,21 +51,75 @@ def _traffic(shape, batch):
     """HBM bytes per blind-rotation launch from the committed counter runs, or
     None when the kernel sources changed since they were taken."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as fh:
             rec = json.load(fh)
-        h = hashlib.sha256()
-        for p in rec["sources"]:
-            with open(os.path.join(ROOT, p), "rb") as fh:
-                h.update(fh.read())
-        if h.hexdigest()[:16] != rec["source_sha"]:
+        if rec.get("sources") != KERNEL_SOURCES or _sources_sha() != rec["source_sha"]:
             continue
         for name, v in rec.items():
             if name.startswith("blind_rotate_kernel") and isinstance(v, dict) \
                     and v.get("batch") == batch and shape == 0:
                 return v["hbm_bytes_per_launch"]
     return None
+
+
+KERNEL_SOURCES = ["paper_2309_09025_amd/csrc/pbs.hip", "paper_2309_09025_amd/csrc/ntt_fp64.h",
+                  "paper_2309_09025_amd/csrc/kernels.h"]
+
+
+def _sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch) of `bench.py --no-networks --copy-mib M` into HBM bytes per
+    launch of each kernel, calibrated by the plain copy of M MiB that run
+    also made (the largest copyBuffer dispatch)."""
+    import csv
+    import glob
+    from collections import Counter, defaultdict
+
+    def per_dispatch(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        vals = defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    vals[r["Kernel_Name"]].append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+        return vals
+
+    fetch, write = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    copy_key = next(k for k in fetch if "copyBuffer" in k)
+    cf = max(v for _, v in fetch[copy_key])
+    cw = max(v for _, v in write[copy_key])
+    copy_kib = copy_mib * 1024.0
+    rec = {"source_sha": _sources_sha(), "sources": KERNEL_SOURCES,
+           "calibration": {"copy_MiB": copy_mib, "fetch_kib": cf, "write_kib": cw,
+                           "fetch_factor": round(copy_kib / cf, 4),
+                           "write_factor": round(copy_kib / cw, 4)}}
+    for name in fetch:
+        if "copyBuffer" in name or name not in write:
+            continue
+        # the dispatches of the timed batch: the most common grid size
+        grid = Counter(g for g, _ in fetch[name]).most_common(1)[0][0]
+        fk = [v for g, v in fetch[name] if g == grid]
+        wk = [v for g, v in write[name] if g == grid]
+        f_kib, w_kib = sum(fk) / len(fk), sum(wk) / len(wk)
+        short = name.split("(")[0].split(" ")[-1].replace("fs::", "") if "<" not in name \
+            else name.split("(")[0].replace("void ", "").replace("fs::", "").replace(" ", "")
+        rec[short] = {"batch": batch, "grid": grid, "dispatches": len(fk),
+                      "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
+                      "hbm_bytes_per_launch": int(1024 * (f_kib * rec["calibration"]["fetch_factor"]
+                                                          + w_kib * rec["calibration"]["write_factor"]))}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
 
 
 def _log(msg):
@@ -186,14 +240,23 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--shape", choices=["a", "b"], default="a")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="bootstrappings the CPU oracle times (0: 2 per host thread)")
+                    help="bootstrappings the CPU oracle times (0: 20 per host thread, ~10 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="time every kernel variant again")
     ap.add_argument("--no-networks", action="store_true",
                     help="only the batched bootstrapping step (no prediction workloads)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_*.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        P = {"a": (630, 1024), "b": (630, 2048)}[args.shape]
+        out = os.path.join(ROOT, "profiles",
+                           f"traffic_batched_pbs_n{P[0]}_N{P[1]}_B{args.batch}.json")
+        rec = ingest_counters(*args.ingest_counters, args.batch, args.copy_mib or 256, out)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the bootstrappings of a batch "
               "are independent; sharding across GPUs is described in DESIGN.md, not built)",
@@ -285,7 +348,7 @@ def main():
         from oracle import oracle as O
         OP = O.SHAPE_A if shape == 0 else O.SHAPE_B
         nt = O.threads()
-        S = min(B, args.cpu_sample or 2 * nt)
+        S = min(B, args.cpu_sample or 20 * nt)
         K = O.keygen(OP, synth.SEED_KEYS, with_ksk=True)
         octs = O.encrypt(OP, K.s, m[:S], synth.SEED_ENC)
         v = O.test_poly(OP.N, OP.p, fire)
