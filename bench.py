@@ -197,9 +197,9 @@ def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):
             "bootstrappings": batch.pbs_count, "pbs_per_s": round(batch.pbs_count / dt, 1)}
 
 
-def serving(F, SV, synth, ctx, P, capacity, requests=48, clients=8, load=0.8):
-    """Poisson arrivals from 8 clients with their own resident keys; hidden
-    256/800 and T 2..8 per request; admission by a budget of 16 requests."""
+def _server(F, SV, synth, ctx, P, clients):
+    """A server with `clients` registered keys (hidden 256/800) and an
+    admission budget of 16 of the largest requests."""
     Wc, nets = _conv_nets(synth, (256, 800))
     base = synth.CONV_SNN
     geom = (base.Ci, base.H, base.Wd, base.stride, base.pad)
@@ -210,26 +210,54 @@ def serving(F, SV, synth, ctx, P, capacity, requests=48, clients=8, load=0.8):
         srv.register(c, evk)
         sks[c] = sk
     srv.budget = 16 * max(srv.request_bytes(h) for h in nets)
-    g = synth.rng(synth.SEED_DATA, 321)
-    rate = load * capacity
-    arr = SV.poisson_arrivals(requests, rate, synth.SEED_DATA)
+    return srv, sks
+
+
+def _serve_once(F, SV, synth, srv, sks, rate, requests, stream):
+    base = synth.CONV_SNN
+    g = synth.rng(synth.SEED_DATA, stream)
+    arr = SV.poisson_arrivals(requests, rate, synth.SEED_DATA + stream)
     reqs = []
     for r in range(requests):
-        c = int(g.integers(0, clients))
+        c = int(g.integers(0, len(sks)))
         T = int(g.integers(2, 9))
         H = 256 if g.integers(0, 2) == 0 else 800
         px = base.data(image_stream=200 + r)[0]
         reqs.append(SV.Request(r, c, F.encrypt(sks[c], px, synth.SEED_ENC, 7000 * r), T, H,
                                float(arr[r])))
+    srv.pbs_count, srv.ticks = 0, 0
     srv.run(reqs, log=_log)
     span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     st = SV.latency_stats(reqs)
-    return {"workload": f"{requests} requests, {clients} clients with resident keys, Poisson "
-                        f"arrivals at {rate:.2f}/s ({load} x uneven-batch capacity), T 2..8, "
-                        f"hidden 256/800, admission budget 16 requests",
+    return {"requests": requests, "arrival_rate_per_s": round(rate, 3),
             "predictions_per_s": round(requests / span, 3), "p50_latency_s": round(st["p50_s"], 3),
-            "p99_latency_s": round(st["p99_s"], 3), "bootstrappings": srv.pbs_count,
-            "resident_key_bytes": srv.key_bytes(), "ticks": srv.ticks}
+            "p99_latency_s": round(st["p99_s"], 3), "max_latency_s": round(st["max_s"], 3),
+            "bootstrappings": srv.pbs_count, "ticks": srv.ticks}
+
+
+def serving(F, SV, synth, ctx, P, capacity, requests=48, clients=8, load=0.8):
+    """Poisson arrivals from 8 clients with their own resident keys; hidden
+    256/800 and T 2..8 per request; admission by a budget of 16 requests."""
+    srv, sks = _server(F, SV, synth, ctx, P, clients)
+    res = _serve_once(F, SV, synth, srv, sks, load * capacity, requests, 321)
+    res.update({"workload": f"{requests} requests, {clients} clients with resident keys, Poisson "
+                            f"arrivals at {res['arrival_rate_per_s']}/s ({load} x uneven-batch "
+                            f"capacity), T 2..8, hidden 256/800, admission budget 16 requests",
+                "resident_key_bytes": srv.key_bytes()})
+    return res
+
+
+def serving_sweep(F, SV, synth, ctx, P, capacity, requests, loads=(0.5, 0.8, 0.95), clients=8):
+    """The serving workload at several offered loads (fractions of the
+    uneven-batch capacity), `requests` requests each."""
+    srv, sks = _server(F, SV, synth, ctx, P, clients)
+    out = {"capacity_predictions_per_s": capacity, "clients": clients,
+           "resident_key_bytes": srv.key_bytes(), "loads": {}}
+    for k, load in enumerate(loads):
+        _log(f"serving sweep: load {load}")
+        out["loads"][str(load)] = _serve_once(F, SV, synth, srv, sks, load * capacity, requests,
+                                              400 + k)
+    return out
 
 
 def main():
@@ -247,6 +275,9 @@ def main():
                     help="only the batched bootstrapping step (no prediction workloads)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serving-sweep", type=int, default=0, metavar="REQUESTS",
+                    help="only the serving workload: REQUESTS requests at 0.5, 0.8 and 0.95 of "
+                         "the measured uneven-batch capacity (one JSON line)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_*.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -275,6 +306,16 @@ def main():
     sk, evk = F.keygen(P, synth.SEED_KEYS)
     ctx = F.Context(0)
     dk = F.evk_upload(ctx, evk)
+    if args.serving_sweep:
+        from paper_2309_09025_amd import network as NW
+        from paper_2309_09025_amd import serve as SV
+        _log("uneven batch of 64 images (capacity)")
+        ub = uneven_batch(F, NW, synth, ctx, dk, sk)
+        sweep = serving_sweep(F, SV, synth, ctx, P, ub["predictions_per_s"], args.serving_sweep)
+        print(json.dumps({"workload": "serving: Poisson arrivals from 8 clients with resident keys, "
+                                      "T 2..8, hidden 256/800, admission budget 16 requests",
+                          "uneven_batch": ub, "sweep": sweep}), flush=True)
+        return
     m = synth.messages(synth.SEED_DATA, B, P.p)
     ct = F.encrypt(sk, m, synth.SEED_ENC)
     fire, _ = F.lif_luts(4, 2, P.p)
