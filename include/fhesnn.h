@@ -162,6 +162,14 @@ FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
 FS_API int fs_br_variants(void);
 FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
 
+/* Batches of at most max_jobs bootstrapping jobs (ciphertexts x program
+ * functions) run each job on two groups of N/16 threads that split the
+ * accumulator's two polynomials and exchange partial products once per CMux
+ * step (same results; lower latency when the batch cannot fill the device).
+ * Default: 4 x the device's compute units.  0 disables the split.  The
+ * previous threshold is stored in *previous unless it is NULL. */
+FS_API int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous);
+
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
  * the exact negacyclic transform on the device; the KSK is copied as is.
  * Synchronous.  The device key is immutable afterwards and may be shared

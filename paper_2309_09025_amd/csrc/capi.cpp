@@ -46,6 +46,10 @@ struct fs_ctx {
   // batches up to this many bootstrappings key-switch inside the blind
   // rotation kernel; larger ones use the batched key-switch kernel
   size_t fuse_max_jobs = 64;
+  // batches up to this many jobs run each job on two polynomial groups
+  // (set at creation to 4 x the device's compute units: below that the
+  // one-group kernel leaves SIMDs idle)
+  size_t split_max_jobs = 0;
   // device copy of the range table of the last multi-key launch
   fs::JobRange* ranges = nullptr;
   size_t ranges_cap = 0;
@@ -215,6 +219,7 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   const size_t jobs = B * nlut;
   auto vit = ctx->br_variant.find(P.N);
   const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  const bool split = jobs <= ctx->split_max_jobs;
   BrArgs br{};
   br.in = in;
   br.tpoly0 = tp[0];
@@ -238,7 +243,8 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
     br.out1 = out1;
     br.plain_add[0] = plain_add[0];
     br.plain_add[1] = plain_add[1];
-    return launch_rc(launch_blind_rotate(P.N, br, jobs, variant, true, st), "blind rotation");
+    return launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, true, st),
+                     "blind rotation");
   }
   if (keyswitch) {
     int rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
@@ -247,7 +253,8 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   } else {
     br.ext = out0;
   }
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, false, st), "blind rotation");
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, false, st),
+                     "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
   ks.in = br.ext;
@@ -393,8 +400,11 @@ int fs_ctx_create(int device, fs_ctx** ctx) {
   int count = 0;
   FS_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(FS_EINVAL, "no such HIP device");
+  int cus = 0;
+  FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   auto* c = new fs_ctx;
   c->device = device;
+  c->split_max_jobs = 4 * (size_t)cus;
   *ctx = c;
   return FS_OK;
 }
@@ -420,6 +430,14 @@ int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs) {
 }
 
 int fs_br_variants(void) { return blind_rotate_variants(); }
+
+int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (previous) *previous = ctx->split_max_jobs;
+  ctx->split_max_jobs = max_jobs;
+  return FS_OK;
+}
 
 int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant) {
   if (!ctx) return fail(FS_EINVAL, "null context");
@@ -639,7 +657,9 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   br.ext = ctx->ext;
   br.ranges = ctx->ranges;
   br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, false, st), "blind rotation");
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, false,
+                                     st),
+                 "blind rotation");
   if (rc) return rc;
   // one batched key switch per key over its adjacent ranges
   size_t a = 0;

@@ -73,8 +73,9 @@ struct KsArgs {
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
                       const double* tw, hipStream_t st);
 int blind_rotate_variants();
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool fused_ks,
-                        hipStream_t st);
+// split: two polynomial groups per job (small batches)
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+                        bool fused_ks, hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 // words per KSK row n+1 rounded up to the 32-word tiles of the matrix-core
 // key switch, and the byte size of its plane layout

@@ -66,18 +66,30 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // roots shared by all threads come from the kernel-argument segment and the
 // per-thread ones are requested one round ahead.  WPE is the number of
 // waves per SIMD the register allocation must allow.
-template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, bool KS>
-__global__ void __launch_bounds__(NttShape<LOGN>::TP, WPE)
+//
+// W = 2 splits one job over two polynomial groups of TP threads (two waves
+// at N = 1024), for batches too small to fill the device: group c
+// decomposes and transforms the digits of D_c only, accumulating partial
+// products for both outputs; once per step the groups swap the partial sums
+// of the other's output through LDS, and group c inverse-transforms and
+// updates ACC_c.  Each group reads only its own ACC_c, so the only
+// cross-group synchronisation is the swap.
+template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, bool KS, int W>
+__global__ void __launch_bounds__(W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
   constexpr int N = S::N, TP = S::TP, ROWS = 2 * L;
   constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr uint32_t NU = LOGN + 1;  // log2(2N)
   constexpr int G = 2 * LIMBS;       // key values per slot and digit row
-  __shared__ double lds[S::LDS_DOUBLES];
+  static_assert(W == 1 || W == 2, "one or two polynomial groups per job");
+  static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
+  __shared__ double lds_all[W][S::LDS_DOUBLES];
   __shared__ uint32_t acc[2][N];
 
-  const int t = threadIdx.x;
+  const int grp = W == 1 ? 0 : (int)threadIdx.x / TP;  // polynomial group
+  const int t = (int)threadIdx.x - grp * TP;
+  double* lds = lds_all[grp];
   const size_t job = blockIdx.x;
   const uint32_t n = a.n;
   const uint64_t g = job / a.nlut;  // ciphertext of this job
@@ -93,6 +105,9 @@ blind_rotate_kernel(BrArgs a) {
   }
   const Tab key(bsk), fwd_tw(a.fwd_tw), inv_tw(a.inv_tw), post(a.post);
   const uint32_t* v = (job % a.nlut) == 0 ? a.tpoly0 : a.tpoly1;
+  // the accumulator polynomials this group decomposes and updates
+  constexpr int NC = W == 1 ? 2 : 1;
+  const int c0 = W == 1 ? 0 : grp;
 
   // gadget rounding offset: sum_{j=1..L} (Bg/2) 2^{32 - j BG} + 2^{31 - L BG}
   uint32_t off = 1u << (31 - L * BG);
@@ -112,8 +127,8 @@ blind_rotate_kernel(BrArgs a) {
       if (src >= 0) val = v[src];
       else if (src + N >= 0) val = 0u - v[src + N];
       else val = v[src + 2 * N];
-      acc[0][j] = 0u;
-      acc[1][j] = val;
+      if (c0 == 0) acc[0][j] = 0u;
+      if (c0 + NC == 2) acc[1][j] = val;
     }
   }
   poly_sync<TP>();
@@ -130,7 +145,7 @@ blind_rotate_kernel(BrArgs a) {
     // byte offset of step i's key slice (< 2^31: n * 2l * 16 * TP * G * 8)
     const uint32_t key_i = i * (uint32_t)(ROWS * 16 * TP * G * 8);
 #pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
+    for (int c = c0; c < c0 + NC; ++c) {
       // D_c = X^{a~} ACC_c - ACC_c plus the gadget offset.  Coefficient j of
       // X^{a~} ACC is ACC[k mod N] with k = j - a~ in (-2N, N), negated when
       // k mod 2N >= N (one wrap past X^N = -1).
@@ -187,10 +202,27 @@ blind_rotate_kernel(BrArgs a) {
         }
       }
     }
+    if constexpr (W == 2) {
+      // swap partial sums: group c keeps the sums for output c and adds the
+      // other group's (both in the same round-C register mapping)
+#pragma unroll
+      for (int lb = 0; lb < LIMBS; ++lb) {
+        const double* mine_other = grp == 0 ? p1[lb] : p0[lb];
+        double* mine = grp == 0 ? p0[lb] : p1[lb];
+        if (lb > 0) __syncthreads();  // the other group has read the previous limb
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds[r * TP + t] = mine_other[r];
+        __syncthreads();
+        const double* theirs = lds_all[1 - grp];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mine[r] += theirs[r * TP + t];
+      }
+      __syncthreads();  // both swaps read before the buffers are reused
+    }
     // inverse transforms; p* hold sums of 2L products of transformed digits
     // (|x| < 2 P, not reduced) with reduced key values: < 5 P
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = c0; c < c0 + NC; ++c) {
       uint32_t upd[16];
 #pragma unroll
       for (int lb = 0; lb < LIMBS; ++lb) {
@@ -207,23 +239,26 @@ blind_rotate_kernel(BrArgs a) {
     }
     poly_sync<TP>();
   }
+  if constexpr (W == 2) __syncthreads();  // the epilogue reads both accumulators
 
   if constexpr (!KS) {
     // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
     uint32_t* out = a.ext + job * (size_t)(N + 1);
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int j = t + TP * r;
+    for (int r = 0; r < 16 / W; ++r) {
+      const int j = tid + W * TP * r;
       out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
     }
-    if (t == 0) out[N] = acc[1][0];
+    if (tid == 0) out[N] = acc[1][0];
   } else {
     // Fused Sample Extraction + Key Switching z -> s.  The extracted mask is
     // a'_0 = ACC_a[0], a'_i = -ACC_a[N-i]; each a'_i is rounded to 16 bits
     // and split into eight base-4 digits (most significant first); digit d
     // of coefficient i at position j selects KSK[i][j][d-1], d = 0 the
     // all-zero row.  The digits are the same for every thread (scalar);
-    // thread t accumulates output words t, t + TP, ... .
+    // thread t accumulates output words t, t + TP, ... .  With two groups,
+    // group c takes coefficients [c N/2, (c+1) N/2) and the sums meet in LDS.
     constexpr int KT = 8, KB = 2, PREC = KT * KB;
     constexpr int WPT = 1024 / TP;  // words per thread, n + 1 <= 1024
     const uint32_t w1 = n + 1;
@@ -232,7 +267,8 @@ blind_rotate_kernel(BrArgs a) {
     for (int k = 0; k < WPT; ++k) o[k] = 0u;
     const uint32_t* __restrict__ ksk = a.ksk;
     const uint32_t* zero = ksk + (size_t)N * KT * 3 * w1;
-    for (int i = 0; i < N; ++i) {
+    const int ibeg = grp * (N / W), iend = ibeg + N / W;
+    for (int i = ibeg; i < iend; ++i) {
       const uint32_t ai = __builtin_amdgcn_readfirstlane(i == 0 ? acc[0][0] : 0u - acc[0][N - i]);
       const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
       const uint32_t* rowi = ksk + (size_t)i * KT * 3 * w1;
@@ -246,6 +282,17 @@ blind_rotate_kernel(BrArgs a) {
           if (w < w1) o[k] -= row[w];
         }
       }
+    }
+    if constexpr (W == 2) {
+      uint32_t* part = reinterpret_cast<uint32_t*>(lds_all[0]);
+      if (grp == 1) {
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) part[k * TP + t] = o[k];
+      }
+      __syncthreads();
+      if (grp == 1) return;
+#pragma unroll
+      for (int k = 0; k < WPT; ++k) o[k] += part[k * TP + t];
     }
     const uint32_t lut = (uint32_t)(job % a.nlut);
     uint32_t* out;
@@ -550,27 +597,37 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // Kernel variants the tuner chooses from: (PF key-slice prefetch point,
 // minimum waves per SIMD the register allocation must allow).
 // N = 1024: (0, 2), (1, 2), (2, 1), (2, 2); N = 2048: (0, 1), (2, 1), (1, 1),
-// (0, 2).
+// (0, 2).  Split launches (two polynomial groups per job) use (1, 2) at
+// N = 1024 and (0, 1) at N = 2048.
 int blind_rotate_variants() { return 4; }
 
 template <bool KS>
-static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipStream_t st) {
+static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+                     hipStream_t st) {
   const dim3 g((uint32_t)jobs);
   if (N == 1024) {
-    switch (variant) {
-      case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, KS><<<g, 64, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS><<<g, 64, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, KS><<<g, 64, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, KS><<<g, 64, 0, st>>>(a); break;
-      default: return -2;
+    if (split) {
+      blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS, 2><<<g, 128, 0, st>>>(a);
+    } else {
+      switch (variant) {
+        case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, KS, 1><<<g, 64, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
+        default: return -2;
+      }
     }
   } else if (N == 2048) {
-    switch (variant) {
-      case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS><<<g, 128, 0, st>>>(a); break;
-      case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, KS><<<g, 128, 0, st>>>(a); break;
-      case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, KS><<<g, 128, 0, st>>>(a); break;
-      case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, KS><<<g, 128, 0, st>>>(a); break;
-      default: return -2;
+    if (split) {
+      blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS, 2><<<g, 256, 0, st>>>(a);
+    } else {
+      switch (variant) {
+        case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, KS, 1><<<g, 128, 0, st>>>(a); break;
+        default: return -2;
+      }
     }
   } else {
     return -1;
@@ -579,11 +636,11 @@ static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, hipS
   return 0;
 }
 
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool fused_ks,
-                        hipStream_t st) {
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+                        bool fused_ks, hipStream_t st) {
   if (jobs == 0) return 0;
-  return fused_ks ? launch_br<true>(N, a, jobs, variant, st)
-                  : launch_br<false>(N, a, jobs, variant, st);
+  return fused_ks ? launch_br<true>(N, a, jobs, variant, split, st)
+                  : launch_br<false>(N, a, jobs, variant, split, st);
 }
 
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {

@@ -67,6 +67,7 @@ SIGNATURES = {
     "fs_encrypt": (_int, [_vp, _i32p, _sz, _u64, _u64, _u32p]),
     "fs_decrypt": (_int, [_vp, _u32p, _sz, _u32, _i32p]),
     "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
+    "fs_ctx_set_split": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "fs_evk_export": (_int, [_vp, _u32p, _u32p]),
     "fs_evk_params": (_int, [_vp, _PP]),
     "fs_secret_free": (None, [_vp]),
@@ -260,6 +261,13 @@ class Context:
 
     def reserve(self, N: int, max_jobs: int):
         _check("fs_ctx_reserve", lib().fs_ctx_reserve(self.h, N, max_jobs))
+
+    def set_split(self, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs use two thread groups per job;
+        returns the previous threshold."""
+        prev = ctypes.c_size_t()
+        _check("fs_ctx_set_split", lib().fs_ctx_set_split(self.h, max_jobs, ctypes.byref(prev)))
+        return prev.value
 
     def set_br_variant(self, N: int, variant: int):
         _check("fs_ctx_set_br_variant", lib().fs_ctx_set_br_variant(self.h, N, variant))

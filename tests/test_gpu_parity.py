@@ -71,11 +71,13 @@ def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     f = O.lut_reset(P.p, 4, 2)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
     ctx.set_br_variant(P.N, variant)
+    split = ctx.set_split(0)  # the one-group kernel of this variant
     try:
         F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
         got = _host(out)
     finally:
         ctx.set_br_variant(P.N, 0)
+        ctx.set_split(split)
     assert np.array_equal(got, O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
 
 
@@ -87,12 +89,38 @@ def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, varian
     f = O.lut_fire(P.p, 4)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
     ctx.set_br_variant(P.N, variant)
+    split = ctx.set_split(0)  # the one-group kernel of this variant
     try:
         F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
         got = _host(out)
     finally:
         ctx.set_br_variant(P.N, 0)
+        ctx.set_split(split)
     assert np.array_equal(got, O.pbs(okeys_b, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
+
+
+@pytest.mark.parametrize("shape,count,keyswitch", [(0, 5, True), (0, 70, True), (0, 9, False),
+                                                     (1, 3, True), (1, 66, True)])
+def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, keyswitch):
+    """Two thread groups per job (small batches) and one group per job give
+    the oracle's bits, with the key switch fused (<= 64 jobs), batched, or
+    not applied."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(shape)
+    ok = okeys_a if shape == 0 else okeys_b
+    m, ct = _pbs_inputs(P, sk, ok, count, first=900 + 97 * shape + count)
+    f = O.lut_reset(P.p, 4, 2)
+    width = P.n + 1 if keyswitch else P.N + 1
+    want = O.pbs(ok, O.test_poly(P.N, P.p, f), ct, keyswitch=keyswitch)
+    prev = ctx.set_split(1 << 20)
+    try:
+        for split in (1 << 20, 0):
+            ctx.set_split(split)
+            out = torch.zeros((count, width), dtype=torch.int32, device="cuda")
+            F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=keyswitch)
+            assert np.array_equal(_host(out), want), split
+    finally:
+        ctx.set_split(prev)
 
 
 def test_pbs_lif_bit_exact(gpu_env, okeys_a):
