@@ -193,7 +193,7 @@ def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"workload": f"{images} synthetic images, T uniform in 2..8, hidden 256 or 800",
-            "predictions_per_s": round(images / dt, 3), "seconds": round(dt, 3),
+            "images": images, "predictions_per_s": round(images / dt, 3), "seconds": round(dt, 3),
             "bootstrappings": batch.pbs_count, "pbs_per_s": round(batch.pbs_count / dt, 1)}
 
 
@@ -412,6 +412,18 @@ def main():
         extra["uneven_batch"] = uneven_batch(F, NW, synth, ctx, dk, sk)
         _log("serving")
         extra["serving"] = serving(F, SV, synth, ctx, P, extra["uneven_batch"]["predictions_per_s"])
+
+    # per prediction workload: the bootstrapping rate as a fraction of the
+    # VALU roofline (same algorithmic count as the batched line), and the
+    # oracle's time for the same work, extrapolated from its measured rate
+    for key in ("single_image", "uneven_batch"):
+        w = extra.get(key)
+        if not w:
+            continue
+        w["roofline_frac"] = round(w["pbs_per_s"] * ops / 1e12 / PEAK_VALU_TOPS, 4)
+        if cpu:
+            pbs_per_pred = w.get("bootstrappings_per_image") or w["bootstrappings"] / w["images"]
+            w["oracle_s_per_prediction_extrapolated"] = round(pbs_per_pred / cpu["value"], 1)
 
     res = {
         "metric": "bootstrappings/sec (n=630,N=1024) + encrypted predictions/sec; p99 latency",
