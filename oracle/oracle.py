@@ -445,6 +445,51 @@ def conv_snn_run(keys: Keys, px_ct, Wc, W1, W2, geom, vth: int, tau: int, T: int
     return I1, steps
 
 
+def lwe_sum_pool(ct, C: int, H: int, W: int, k: int):
+    """Sum of each k x k window (stride k) of a [C*H*W] grid of ciphertexts:
+    the numerator of the average pool, whose division by n = k^2 moves into
+    the next layer's weights (Sec. 3.3, the average-pooling equation: the
+    weights are discretised with scale theta / n and multiply the window
+    sum of spikes)."""
+    ct = np.asarray(ct, np.uint32).reshape(C, H, W, -1)
+    Ho, Wo = H // k, W // k
+    out = np.zeros((C, Ho, Wo, ct.shape[-1]), np.uint64)
+    for dy in range(k):
+        for dx in range(k):
+            out += ct[:, dy:dy + k * Ho:k, dx:dx + k * Wo:k, :]
+    return (out & 0xFFFFFFFF).astype(np.uint32).reshape(C * Ho * Wo, -1)
+
+
+def paper_csnn_run(keys: Keys, px_ct, Wc, W1, W2, geom, pool: int, vth: int, tau: int, T: int,
+                   nthreads=None):
+    """The paper's CSNN (Sec. 3.1) on ciphertexts: conv (LIF) -> average pool
+    (window sum, Sec. 3.3) -> FC (LIF) -> FC (LIF), scores = the encrypted
+    spike counts of the output layer, sum_t LWE(2S[t]).  Two bootstrappings
+    per LIF neuron per step (Table 1).  geom = (Ci, H, Wd, stride, pad)."""
+    Ci, H, Wd, st, pd = geom
+    Co, _, K, _ = np.asarray(Wc).shape
+    Ho = (H + 2 * pd - K) // st + 1
+    Wo = (Wd + 2 * pd - K) // st + 1
+    I1 = lwe_conv2d(Wc, px_ct, Ci, H, Wd, st, pd)
+    w = I1.shape[1]
+    V1 = zero_ct(*I1.shape)
+    V2 = zero_ct(W1.shape[0], w)
+    V3 = zero_ct(W2.shape[0], w)
+    score = zero_ct(W2.shape[0], w)
+    steps = []
+    for _ in range(T):
+        H1 = (V1 + I1).astype(np.uint32)
+        S1, V1 = lif_step(keys, vth, tau, H1, nthreads)
+        H2 = lwe_linear(W1, lwe_sum_pool(S1, Co, Ho, Wo, pool), add=V2)
+        S2, V2 = lif_step(keys, vth, tau, H2, nthreads)
+        H3 = lwe_linear(W2, S2, add=V3)
+        S3, V3 = lif_step(keys, vth, tau, H3, nthreads)
+        score = (score.astype(np.uint64) + S3).astype(np.uint32)
+        steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, H3=H3, S3=S3, V3=V3,
+                          score=score.copy()))
+    return I1, steps
+
+
 # ---------------------------------------------------------------- plaintext SNN (mod p)
 
 def plain_lif_layer_run(p: int, I, vth: int, tau: int, T: int):
@@ -496,4 +541,38 @@ def plain_conv_snn_run(p: int, px, Wc, W1, W2, geom, vth: int, tau: int, T: int)
         V2 = plain_reset(p, vth, tau, H2)
         score = (score + W2 @ S2) % p
         steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, score=score.copy()))
+    return I1, steps
+
+
+def plain_paper_csnn_run(p: int, px, Wc, W1, W2, geom, pool: int, vth: int, tau: int, T: int):
+    """paper_csnn_run on integers mod p."""
+    Ci, H, Wd, st, pd = geom
+    Wc = np.asarray(Wc, np.int64)
+    Co, _, K, _ = Wc.shape
+    Ho = (H + 2 * pd - K) // st + 1
+    Wo = (Wd + 2 * pd - K) // st + 1
+    I1 = plain_conv2d(Wc, px, Ci, H, Wd, st, pd) % p
+    W1 = np.asarray(W1, np.int64)
+    W2 = np.asarray(W2, np.int64)
+    V1 = np.zeros_like(I1)
+    V2 = np.zeros(W1.shape[0], np.int64)
+    V3 = np.zeros(W2.shape[0], np.int64)
+    score = np.zeros(W2.shape[0], np.int64)
+    steps = []
+    for _ in range(T):
+        H1 = (V1 + I1) % p
+        S1 = plain_fire(p, vth, H1)
+        V1 = plain_reset(p, vth, tau, H1)
+        g = S1.reshape(Co, Ho, Wo)
+        pooled = sum(g[:, dy:dy + pool * (Ho // pool):pool, dx:dx + pool * (Wo // pool):pool]
+                     for dy in range(pool) for dx in range(pool)).reshape(-1)
+        H2 = (V2 + W1 @ pooled) % p
+        S2 = plain_fire(p, vth, H2)
+        V2 = plain_reset(p, vth, tau, H2)
+        H3 = (V3 + W2 @ S2) % p
+        S3 = plain_fire(p, vth, H3)
+        V3 = plain_reset(p, vth, tau, H3)
+        score = (score + S3) % p
+        steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, H3=H3, S3=S3, V3=V3,
+                          score=score.copy()))
     return I1, steps

@@ -118,6 +118,7 @@ class ConvSNN:
         self.H2, self.V2, self.S2 = (_zeros(self.hidden, w) for _ in range(3))
         self.score = _zeros(self.classes, w)
         self.capture = capture
+        self.graph = None
         self.pbs_count = 0
         ctx.reserve(P.N, 2 * max(self.l1, self.hidden))
 
@@ -136,15 +137,92 @@ class ConvSNN:
                      self.stride, self.pad)
         for b in (self.V1, self.V2, self.score):
             b.zero_()
-        g = StepGraph(self._step, self.capture)
+        if self.graph is None:  # the step reads and writes the same buffers for every image
+            self.graph = StepGraph(self._step, self.capture)
         steps = []
         for _ in range(T):
-            g.run()
+            self.graph.run()
             self.pbs_count += 2 * (self.l1 + self.hidden)
             if record:
                 torch.cuda.synchronize()
                 steps.append({k: F.to_host(getattr(self, k)) for k in
                               ("H1", "S1", "V1", "H2", "S2", "V2", "score")})
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
+
+def fold_avg_pool(W1: np.ndarray, C: int, H: int, W: int, k: int) -> np.ndarray:
+    """Weights of an FC layer over a k x k sum pool, moved onto the unpooled
+    grid (Sec. 3.3: the pool's division goes into the next layer's weight
+    scale, so the layer multiplies window sums of spikes): returns
+    [O][C*H*W] with W1f[o][c, y, x] = W1[o][c, y // k, x // k] (zero for rows
+    and columns the pool does not cover).  A product with W1f is then exactly
+    the product of W1 with the window sums."""
+    O_, _ = W1.shape
+    Hp, Wp = H // k, W // k
+    W1 = np.asarray(W1, np.int32).reshape(O_, C, Hp, Wp)
+    Wf = np.zeros((O_, C, H, W), np.int32)
+    Wf[:, :, : k * Hp, : k * Wp] = np.repeat(np.repeat(W1, k, axis=2), k, axis=3)
+    return Wf.reshape(O_, C * H * W)
+
+
+class PaperCSNN:
+    """The paper's CSNN on one encrypted image (Sec. 3.1): conv (LIF) ->
+    average pool -> FC (LIF) -> FC (LIF) with the output layer's spikes
+    counted as scores.  The pool is folded into FC1's weights
+    (fold_avg_pool), so a timestep is the same five library calls as
+    ConvSNN's plus the output layer; each timestep is one HIP graph."""
+
+    def __init__(self, ctx, dk, Wc, W1, W2, geom, pool: int = 2, lif: LifSpec = LifSpec(),
+                 capture: bool = True):
+        self.ctx, self.dk, self.lif = ctx, dk, lif
+        P = dk.params
+        self.width = w = P.n + 1
+        self.Ci, self.H, self.Wd, self.stride, self.pad = geom
+        Co, _, K, _ = Wc.shape
+        Ho = (self.H + 2 * self.pad - K) // self.stride + 1
+        Wo = (self.Wd + 2 * self.pad - K) // self.stride + 1
+        self.l1 = Co * Ho * Wo
+        self.hidden, self.classes = W1.shape[0], W2.shape[0]
+        self.Wc = F.to_device(np.ascontiguousarray(Wc, np.int32))
+        self.W1 = F.to_device(fold_avg_pool(W1, Co, Ho, Wo, pool))
+        self.W2 = F.to_device(np.ascontiguousarray(W2, np.int32))
+        self.I1, self.H1, self.V1, self.S1 = (_zeros(self.l1, w) for _ in range(4))
+        self.H2, self.V2, self.S2 = (_zeros(self.hidden, w) for _ in range(3))
+        self.H3, self.V3, self.S3 = (_zeros(self.classes, w) for _ in range(3))
+        self.score = _zeros(self.classes, w)
+        self.capture = capture
+        self.graph = None
+        self.pbs_count = 0
+        ctx.reserve(P.N, 2 * max(self.l1, self.hidden))
+
+    def _step(self):
+        c, dk, L = self.ctx, self.dk, self.lif
+        F.lwe_add(c, self.V1, self.I1, self.H1)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        F.lwe_linear(c, self.W2, self.S2, self.H3, add=self.V3)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H3, self.S3, self.V3)
+        F.lwe_add(c, self.score, self.S3, self.score)
+
+    def run(self, px_ct, T: int, record: bool = False):
+        """Returns the encrypted spike counts (host) and, if record,
+        per-step host copies of every state buffer."""
+        F.lwe_conv2d(self.ctx, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd,
+                     self.stride, self.pad)
+        for b in (self.V1, self.V2, self.V3, self.score):
+            b.zero_()
+        if self.graph is None:
+            self.graph = StepGraph(self._step, self.capture)
+        steps = []
+        for _ in range(T):
+            self.graph.run()
+            self.pbs_count += 2 * (self.l1 + self.hidden + self.classes)
+            if record:
+                torch.cuda.synchronize()
+                steps.append({k: F.to_host(getattr(self, k)) for k in
+                              ("H1", "S1", "V1", "H2", "S2", "V2", "H3", "S3", "V3", "score")})
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 

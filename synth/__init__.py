@@ -129,6 +129,63 @@ CONV_SNN = ConvSNN()
 CONV_SNN_MINI = ConvSNN(H=8, Wd=8, Co=2, K=3, stride=2, pad=1, hidden=8, classes=4, T=2)
 
 
+@dataclass(frozen=True)
+class PaperCSNN:
+    """The CSNN of the paper (Sec. 3.1): conv Ci->Co KxK stride s pad pd
+    (LIF) -> average pool PxP -> FC (LIF) -> FC (LIF), the output layer's
+    spikes counted as scores; synthetic integer weights in [w_lo, w_hi]."""
+    H: int = 28
+    Wd: int = 28
+    Ci: int = 1
+    Co: int = 10
+    K: int = 8
+    stride: int = 2
+    pad: int = 1
+    pool: int = 2
+    hidden: int = 160
+    classes: int = 10
+    w_lo: int = -8
+    w_hi: int = 8
+    vth: int = 4
+    tau: int = 2
+    T: int = 4
+
+    @property
+    def Ho(self):
+        return (self.H + 2 * self.pad - self.K) // self.stride + 1
+
+    @property
+    def Wo(self):
+        return (self.Wd + 2 * self.pad - self.K) // self.stride + 1
+
+    @property
+    def l1(self):
+        return self.Co * self.Ho * self.Wo
+
+    @property
+    def pooled(self):
+        return self.Co * (self.Ho // self.pool) * (self.Wo // self.pool)
+
+    def pbs_count(self) -> int:
+        """Two bootstrappings per LIF neuron per step (all three layers)."""
+        return 2 * (self.l1 + self.hidden + self.classes) * self.T
+
+    def data(self, seed: int = SEED_DATA, image_stream: int = 0):
+        if self.H == 28 and self.Wd == 28:
+            px = quantise_pixels(image_like_digit(seed, image_stream))
+        else:
+            px = uniform_int(seed, self.Ci * self.H * self.Wd, 0, 15, stream=20 + image_stream)
+        Wc = uniform_int(seed, (self.Co, self.Ci, self.K, self.K), self.w_lo, self.w_hi, stream=13)
+        W1 = uniform_int(seed, (self.hidden, self.pooled), self.w_lo, self.w_hi, stream=14)
+        W2 = uniform_int(seed, (self.classes, self.hidden), self.w_lo, self.w_hi, stream=15)
+        return px, Wc, W1, W2
+
+
+PAPER_CSNN = PaperCSNN()
+# the same topology at a size the oracle runs end to end
+PAPER_CSNN_MINI = PaperCSNN(H=8, Wd=8, Co=2, K=4, stride=2, pad=1, hidden=6, classes=3, T=2)
+
+
 def uneven_batch(seed: int = SEED_DATA, images: int = 64):
     """Per-image timestep counts in {2..8} and hidden widths in {256, 800}."""
     g = rng(seed, 77)

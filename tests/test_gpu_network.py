@@ -113,3 +113,67 @@ def test_uneven_batch_equals_images_alone(gpu_env):
                            NW.LifSpec(base.vth, base.tau), capture=False)
         score, _ = alone.run(cts[k], Ts[k])
         assert np.array_equal(got[k], score), k
+
+
+@pytest.mark.parametrize("capture", [False, True])
+def test_paper_csnn_mini_bit_exact_over_two_images(gpu_env, okeys_a, capture):
+    """The paper's topology (conv -> pool folded into FC1 -> FC -> FC, all
+    LIF, spike-count scores) at a size the oracle runs end to end; the same
+    network object evaluates two images (the step graph is reused)."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.PAPER_CSNN_MINI
+    _, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau),
+                       capture=capture)
+    for img in range(2):
+        px = cfg.data(image_stream=img)[0]
+        score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC, 4000 * img)), cfg.T,
+                               record=True)
+        _, osteps = O.paper_csnn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC,
+                                                        4000 * img),
+                                     Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T)
+        for t in range(cfg.T):
+            for k in ("H1", "S1", "V1", "H2", "S2", "V2", "H3", "S3", "V3", "score"):
+                assert np.array_equal(steps[t][k], osteps[t][k]), (img, t, k)
+        assert np.array_equal(score, osteps[-1]["score"])
+    assert net.pbs_count == 2 * cfg.pbs_count()
+
+
+def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
+    """The paper's CSNN at full size (28x28, conv 1->10 8x8 s2 p1, pool 2,
+    FC 360->160, FC 160->10, T = 4; 3220 T bootstrappings, Table 1).  The
+    oracle recomputes the conv current and the T-step chains of sampled
+    first-layer neurons; the pooled FC (folded weights on the GPU, window
+    sums then FC on the oracle) and the output layer are checked as linear
+    maps of the GPU's own spikes; every bootstrapped output decrypts into its
+    function's range."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.PAPER_CSNN
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau))
+    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    assert net.pbs_count == cfg.pbs_count() == 3220 * cfg.T
+    octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
+    I1 = O.lwe_conv2d(Wc, octs, cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    sample = [0, 13, 143, 144, 1000, 1439]
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I1[sample], cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        assert np.array_equal(steps[t]["H1"][sample], Hs[t]), t
+        assert np.array_equal(steps[t]["S1"][sample], Ss[t]), t
+        assert np.array_equal(steps[t]["V1"][sample], Vs[t]), t
+        pooled = O.lwe_sum_pool(steps[t]["S1"], cfg.Co, cfg.Ho, cfg.Wo, cfg.pool)
+        V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.hidden, P.n + 1)
+        assert np.array_equal(steps[t]["H2"], O.lwe_linear(W1, pooled, add=V2prev)), t
+        V3prev = steps[t - 1]["V3"] if t else O.zero_ct(cfg.classes, P.n + 1)
+        assert np.array_equal(steps[t]["H3"], O.lwe_linear(W2, steps[t]["S2"], add=V3prev)), t
+        for k in ("S1", "S2", "S3"):
+            assert set(np.unique(F.decrypt(sk, steps[t][k]))) <= {0, 2}, (t, k)
+        for k in ("V1", "V2", "V3"):
+            assert set(np.unique(F.decrypt(sk, steps[t][k]))) <= {0, 1, 2, -1, -2}, (t, k)
+    total = sum(steps[t]["S3"].astype(np.uint64) for t in range(cfg.T)) & 0xFFFFFFFF
+    assert np.array_equal(score, total.astype(np.uint32))
+

@@ -21,3 +21,50 @@ def test_tiny_lif_layer_encrypted_equals_plaintext(okeys_a):
         assert np.array_equal(O.decrypt(P.p, okeys_a.s, Hs[t]), O.centred(P.p, pH[t])), t
         assert np.array_equal(O.decrypt(P.p, okeys_a.s, Ss[t]), O.centred(P.p, pS[t])), t
         assert np.array_equal(O.decrypt(P.p, okeys_a.s, Vs[t]), O.centred(P.p, pV[t])), t
+
+
+def test_sum_pool_decrypts_to_window_sums(okeys_a):
+    """Average-pool numerator on ciphertexts (Sec. 3.3): the window sums of
+    the decrypted grid, computed here by reshaping into k x k blocks."""
+    P = O.SHAPE_A
+    C, H, W, k = 2, 6, 6, 2
+    m = synth.uniform_int(synth.SEED_DATA, C * H * W, 0, 2, stream=61)
+    ct = O.encrypt(P, okeys_a.s, m, synth.SEED_ENC, 3000)
+    got = O.decrypt(P.p, okeys_a.s, O.lwe_sum_pool(ct, C, H, W, k))
+    want = m.reshape(C, H // k, k, W // k, k).sum(axis=(2, 4)).reshape(-1)
+    assert np.array_equal(got, O.centred(P.p, want))
+
+
+def test_paper_csnn_counts_match_table_1():
+    """Table 1: (1440 x 2 + 2 x 160 + 2 x 10) T bootstrappings per image."""
+    c = synth.PAPER_CSNN
+    assert (c.l1, c.pooled) == (1440, 360)
+    assert c.pbs_count() == (1440 * 2 + 2 * 160 + 2 * 10) * c.T
+
+
+def test_paper_csnn_oracle_first_layer_equals_plaintext(okeys_a):
+    """A small instance of the paper's topology on the oracle: the first LIF
+    layer (noise 2^-15 x conv weights, far inside the window) decrypts spike
+    for spike to the plaintext network, and every stored step is the
+    recurrence of Theorem 3.1 layer by layer (the pooled FC input is the
+    window sum of the layer-1 spikes).  Deeper layers sum many bootstrapping
+    outputs (noise 2^-8.3 each) with weights up to 8: their decryptions are
+    not pinned (the same holds for the paper's network without its trained,
+    discretised weights)."""
+    P = O.SHAPE_A
+    cfg = synth.PaperCSNN(H=6, Wd=6, Co=2, K=4, stride=2, pad=1, hidden=4, classes=2, T=2)
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    ct = O.encrypt(P, okeys_a.s, px, synth.SEED_ENC)
+    I1, steps = O.paper_csnn_run(okeys_a, ct, Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T)
+    _, psteps = O.plain_paper_csnn_run(P.p, px, Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1"):
+            assert np.array_equal(O.decrypt(P.p, okeys_a.s, steps[t][k]),
+                                  O.centred(P.p, psteps[t][k])), (t, k)
+        pooled = O.lwe_sum_pool(steps[t]["S1"], cfg.Co, cfg.Ho, cfg.Wo, cfg.pool)
+        V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.hidden, P.n + 1)
+        assert np.array_equal(steps[t]["H2"], O.lwe_linear(W1, pooled, add=V2prev))
+        V3prev = steps[t - 1]["V3"] if t else O.zero_ct(cfg.classes, P.n + 1)
+        assert np.array_equal(steps[t]["H3"], O.lwe_linear(W2, steps[t]["S2"], add=V3prev))
+
