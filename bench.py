@@ -122,6 +122,26 @@ def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path):
     return rec
 
 
+def _physical_cores():
+    """Physical cores of the host (distinct core ids per socket), or None."""
+    try:
+        cores = set()
+        phys = core = None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("physical id"):
+                    phys = line.split(":")[1].strip()
+                elif line.startswith("core id"):
+                    core = line.split(":")[1].strip()
+                elif not line.strip():
+                    if core is not None:
+                        cores.add((phys, core))
+                    phys = core = None
+        return len(cores) or None
+    except OSError:
+        return None
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -174,6 +194,27 @@ def single_image(F, NW, synth, ctx, dk, sk, images=3):
             "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
             "bootstrappings_per_image": cfg.pbs_count(),
             "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+
+
+def tiny_lif(F, NW, synth, ctx, dk, sk, reps=5):
+    """The tiny LIF layer: 64 encrypted 3-bit inputs, 32 LIF neurons,
+    T = 2 (128 bootstrappings), one step graph; latency of a whole run."""
+    import torch
+    cfg = synth.TinyLIF()
+    x, W = cfg.data()
+    d_x = F.to_device(F.encrypt(sk, x, synth.SEED_ENC))
+    net = NW.LifLayerNet(ctx, dk, W, NW.LifSpec(cfg.vth, cfg.tau), capture=True)
+    net.run(d_x, cfg.T, record=False)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.run(d_x, cfg.T, record=False)
+    torch.cuda.synchronize()
+    m = (time.perf_counter() - t0) / reps
+    return {"workload": "tiny LIF layer: 64 encrypted 3-bit inputs, W 32x64 in [-8,8], "
+                        "32 LIF neurons (V_th 4, tau 2), T=2",
+            "latency_ms": round(m * 1e3, 2), "bootstrappings": 2 * 32 * cfg.T,
+            "pbs_per_s": round(2 * 32 * cfg.T / m, 1)}
 
 
 def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
@@ -424,8 +465,12 @@ def main():
         tc = time.perf_counter()
         ores = O.pbs(K, v, octs, keyswitch=True, nthreads=nt)
         cdt = time.perf_counter() - tc
+        t1 = time.perf_counter()
+        O.pbs(K, v, octs[:1], keyswitch=True, nthreads=1)
+        single = time.perf_counter() - t1
         cpu = {"value": round(S / cdt, 3), "unit": "bootstrappings/sec", "cores": nt,
-               "kind": "oracle",
+               "kind": "oracle", "single_thread_s_per_pbs": round(single, 3),
+               "host_logical_cpus": os.cpu_count(), "host_physical_cores": _physical_cores(),
                "sample": f"{S} of the {B} bootstrappings (same inputs, keys and test polynomial), "
                          f"{cdt:.1f} s on {nt} threads",
                "parity_on_sample": bool(np.array_equal(ores, out[:S]))}
@@ -434,6 +479,8 @@ def main():
     if not args.no_networks and shape == 0:
         from paper_2309_09025_amd import network as NW
         from paper_2309_09025_amd import serve as SV
+        _log("tiny LIF layer")
+        extra["tiny_lif"] = tiny_lif(F, NW, synth, ctx, dk, sk)
         _log("single-image conv SNN")
         extra["single_image"] = single_image(F, NW, synth, ctx, dk, sk)
         _log("paper CSNN topology, single image")

@@ -43,9 +43,6 @@ struct fs_ctx {
   std::map<uint32_t, fs::UniTw> table_uni;
   // blind-rotation kernel variant per ring degree (chosen by the tuner)
   std::map<uint32_t, int> br_variant;
-  // batches up to this many bootstrappings key-switch inside the blind
-  // rotation kernel; larger ones use the batched key-switch kernel
-  size_t fuse_max_jobs = 64;
   // batches up to this many jobs run each job on two polynomial groups
   // (set at creation to 4 x the device's compute units: below that the
   // one-group kernel leaves SIMDs idle)
@@ -231,21 +228,6 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   br.inv_tw = dk->inv_tw;
   br.post = dk->post;
   br.uni = dk->uni;
-  // key switching fused into the blind-rotation epilogue for the built-in
-  // digit shape (t = 8, base 4, n + 1 <= 1024)
-  // (one launch; best for small batches, where the rows a sample reads
-  // are not shared with other samples anyway)
-  const bool fuse = keyswitch && jobs <= ctx->fuse_max_jobs && P.ks_t == 8 &&
-                    P.ks_base_bit == 2 && P.n + 1 <= 1024;
-  if (fuse) {
-    br.ksk = dk->ksk;
-    br.out0 = out0;
-    br.out1 = out1;
-    br.plain_add[0] = plain_add[0];
-    br.plain_add[1] = plain_add[1];
-    return launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, true, st),
-                     "blind rotation");
-  }
   if (keyswitch) {
     int rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
     if (rc) return rc;
@@ -253,8 +235,7 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   } else {
     br.ext = out0;
   }
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, false, st),
-                     "blind rotation");
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, st), "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
   ks.in = br.ext;
@@ -469,8 +450,7 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   const size_t bsk_ntt = bsk_words * limbs;  // doubles
   hipError_t e = hipMalloc(&dk->bsk, bsk_ntt * sizeof(double));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: BSK allocation failed"));
-  // the KSK is followed by one all-zero row (digit value 0 in the fused key switch)
-  e = hipMalloc(&dk->ksk, (evk->ksk.size() + P.n + 1) * sizeof(uint32_t));
+  e = hipMalloc(&dk->ksk, evk->ksk.size() * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
   const size_t planes = fs::ksk_planes_bytes(P.N, P.n);
   e = hipMalloc(&dk->kskp, planes);
@@ -483,8 +463,6 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   if (e == hipSuccess)
     e = hipMemcpy(dk->ksk, evk->ksk.data(), evk->ksk.size() * sizeof(uint32_t),
                   hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemset(dk->ksk + evk->ksk.size(), 0, (P.n + 1) * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: copy"));
   rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
                  "BSK conversion");
@@ -657,8 +635,7 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   br.ext = ctx->ext;
   br.ranges = ctx->ranges;
   br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, false,
-                                     st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, st),
                  "blind rotation");
   if (rc) return rc;
   // one batched key switch per key over its adjacent ranges

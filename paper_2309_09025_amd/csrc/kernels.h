@@ -42,13 +42,8 @@ struct BrArgs {
   const double* fwd_tw;   // [N] psi^{brv(k)}
   const double* inv_tw;   // [N/2] omega^{-e}
   const double* post;     // [N] psi^{-j} N^{-1}
-  uint32_t* ext;          // [jobs][N+1] extracted samples under z (not fused)
+  uint32_t* ext;          // [jobs][N+1] extracted samples under z
   UniTw uni;              // roots shared by all threads (scalar operands)
-  // fused sample extraction + key switch (t = 8 digits of base 4):
-  const uint32_t* ksk;    // [N][8][3][n+1] followed by one all-zero row
-  uint32_t* out0;         // program function 0 outputs, [jobs/nlut][n+1]
-  uint32_t* out1;         // program function 1 outputs (nlut == 2)
-  uint32_t plain_add[2];  // Delta * c added to b per program function
   // multi-key launch: per-range inputs and keys (in and bsk unused)
   const JobRange* ranges;
   uint32_t nranges;
@@ -75,7 +70,7 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 int blind_rotate_variants();
 // split: two polynomial groups per job (small batches)
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
-                        bool fused_ks, hipStream_t st);
+                        hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 // words per KSK row n+1 rounded up to the 32-word tiles of the matrix-core
 // key switch, and the byte size of its plane layout

@@ -57,7 +57,8 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 //       the two NTT-domain TGSW_i row entries and accumulate
 //   inverse NTT of the two accumulators -> exact integers -> ACC_c +=
 // Initialization ACC = (0, X^{-b~} v) and sample extraction of
-// coefficient 0 are fused at both ends.
+// coefficient 0 are fused at both ends; the key switch of the batch follows
+// in keyswitch_mfma_kernel.
 //
 // Latency: the key slice of a digit row (16 registers x 2*limbs values per
 // thread) is requested at a point set by PF and consumed after the row's
@@ -74,7 +75,7 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // of the other's output through LDS, and group c inverse-transforms and
 // updates ACC_c.  Each group reads only its own ACC_c, so the only
 // cross-group synchronisation is the swap.
-template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, bool KS, int W>
+template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W>
 __global__ void __launch_bounds__(W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
@@ -239,76 +240,17 @@ blind_rotate_kernel(BrArgs a) {
     }
     poly_sync<TP>();
   }
-  if constexpr (W == 2) __syncthreads();  // the epilogue reads both accumulators
+  if constexpr (W == 2) __syncthreads();  // the extraction reads both accumulators
 
-  if constexpr (!KS) {
-    // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
-    uint32_t* out = a.ext + job * (size_t)(N + 1);
-    const int tid = threadIdx.x;
+  // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
+  uint32_t* out = a.ext + job * (size_t)(N + 1);
+  const int tid = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < 16 / W; ++r) {
-      const int j = tid + W * TP * r;
-      out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
-    }
-    if (tid == 0) out[N] = acc[1][0];
-  } else {
-    // Fused Sample Extraction + Key Switching z -> s.  The extracted mask is
-    // a'_0 = ACC_a[0], a'_i = -ACC_a[N-i]; each a'_i is rounded to 16 bits
-    // and split into eight base-4 digits (most significant first); digit d
-    // of coefficient i at position j selects KSK[i][j][d-1], d = 0 the
-    // all-zero row.  The digits are the same for every thread (scalar);
-    // thread t accumulates output words t, t + TP, ... .  With two groups,
-    // group c takes coefficients [c N/2, (c+1) N/2) and the sums meet in LDS.
-    constexpr int KT = 8, KB = 2, PREC = KT * KB;
-    constexpr int WPT = 1024 / TP;  // words per thread, n + 1 <= 1024
-    const uint32_t w1 = n + 1;
-    uint32_t o[WPT];
-#pragma unroll
-    for (int k = 0; k < WPT; ++k) o[k] = 0u;
-    const uint32_t* __restrict__ ksk = a.ksk;
-    const uint32_t* zero = ksk + (size_t)N * KT * 3 * w1;
-    const int ibeg = grp * (N / W), iend = ibeg + N / W;
-    for (int i = ibeg; i < iend; ++i) {
-      const uint32_t ai = __builtin_amdgcn_readfirstlane(i == 0 ? acc[0][0] : 0u - acc[0][N - i]);
-      const uint32_t abar = (ai + (1u << (31 - PREC))) >> (32 - PREC);
-      const uint32_t* rowi = ksk + (size_t)i * KT * 3 * w1;
-#pragma unroll
-      for (int j = 0; j < KT; ++j) {
-        const uint32_t d = (abar >> ((KT - 1 - j) * KB)) & 3u;
-        const uint32_t* row = d ? rowi + (size_t)(j * 3 + d - 1) * w1 : zero;
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) {
-          const uint32_t w = t + TP * k;
-          if (w < w1) o[k] -= row[w];
-        }
-      }
-    }
-    if constexpr (W == 2) {
-      uint32_t* part = reinterpret_cast<uint32_t*>(lds_all[0]);
-      if (grp == 1) {
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) part[k * TP + t] = o[k];
-      }
-      __syncthreads();
-      if (grp == 1) return;
-#pragma unroll
-      for (int k = 0; k < WPT; ++k) o[k] += part[k * TP + t];
-    }
-    const uint32_t lut = (uint32_t)(job % a.nlut);
-    uint32_t* out;
-    if (a.ranges) {
-      const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
-      out = (lut == 0 ? rg.out0 : rg.out1) + (g - rg.first) * (size_t)w1;
-    } else {
-      out = (lut == 0 ? a.out0 : a.out1) + g * (size_t)w1;
-    }
-    const uint32_t bprime = acc[1][0] + a.plain_add[lut];
-#pragma unroll
-    for (int k = 0; k < WPT; ++k) {
-      const uint32_t w = t + TP * k;
-      if (w < w1) out[w] = o[k] + (w == n ? bprime : 0u);
-    }
+  for (int r = 0; r < 16 / W; ++r) {
+    const int j = tid + W * TP * r;
+    out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
   }
+  if (tid == 0) out[N] = acc[1][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -601,31 +543,31 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // N = 1024 and (0, 1) at N = 2048.
 int blind_rotate_variants() { return 4; }
 
-template <bool KS>
-static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
-                     hipStream_t st) {
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+                        hipStream_t st) {
+  if (jobs == 0) return 0;
   const dim3 g((uint32_t)jobs);
   if (N == 1024) {
     if (split) {
-      blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS, 2><<<g, 128, 0, st>>>(a);
+      blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);
     } else {
       switch (variant) {
-        case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
-        case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
-        case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, KS, 1><<<g, 64, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, KS, 1><<<g, 64, 0, st>>>(a); break;
+        case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1><<<g, 64, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1><<<g, 64, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1><<<g, 64, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, 1><<<g, 64, 0, st>>>(a); break;
         default: return -2;
       }
     }
   } else if (N == 2048) {
     if (split) {
-      blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS, 2><<<g, 256, 0, st>>>(a);
+      blind_rotate_kernel<11, 2, 10, 2, 0, 1, 2><<<g, 256, 0, st>>>(a);
     } else {
       switch (variant) {
-        case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
-        case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
-        case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, KS, 1><<<g, 128, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, KS, 1><<<g, 128, 0, st>>>(a); break;
+        case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, 1><<<g, 128, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, 1><<<g, 128, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, 1><<<g, 128, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
         default: return -2;
       }
     }
@@ -634,13 +576,6 @@ static int launch_br(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool
   }
   FS_LAUNCH_CHECK();
   return 0;
-}
-
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
-                        bool fused_ks, hipStream_t st) {
-  if (jobs == 0) return 0;
-  return fused_ks ? launch_br<true>(N, a, jobs, variant, split, st)
-                  : launch_br<false>(N, a, jobs, variant, split, st);
 }
 
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st) {

@@ -74,6 +74,7 @@ class LifLayerNet:
         self.V = _zeros(self.O, self.width)
         self.S = _zeros(self.O, self.width)
         self.capture = capture
+        self.graph = None
         self.pbs_count = 0
         ctx.reserve(P.N, 2 * self.O)
 
@@ -85,10 +86,11 @@ class LifLayerNet:
         """x_ct: device [inputs][n+1].  Returns per-step host copies (H, 2S, V)."""
         F.lwe_linear(self.ctx, self.W, x_ct, self.I)
         self.V.zero_()
-        g = StepGraph(self._step, self.capture)
+        if self.graph is None:  # the step reads and writes the same buffers for every input
+            self.graph = StepGraph(self._step, self.capture)
         out = []
         for _ in range(T):
-            g.run()
+            self.graph.run()
             self.pbs_count += 2 * self.O
             if record:
                 torch.cuda.synchronize()

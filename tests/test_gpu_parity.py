@@ -103,8 +103,7 @@ def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, varian
                                                      (1, 3, True), (1, 66, True)])
 def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, keyswitch):
     """Two thread groups per job (small batches) and one group per job give
-    the oracle's bits, with the key switch fused (<= 64 jobs), batched, or
-    not applied."""
+    the oracle's bits, with and without the key switch."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(shape)
     ok = okeys_a if shape == 0 else okeys_b
@@ -136,8 +135,8 @@ def test_pbs_lif_bit_exact(gpu_env, okeys_a):
 
 
 def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
-    """37 neurons = 74 bootstrappings: past the fused-key-switch limit, so
-    the batched key-switch kernel runs, with a ragged last block."""
+    """37 neurons = 74 bootstrappings: the key switch's 64-sample groups
+    end in a ragged last group."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
     m, ct = _pbs_inputs(P, sk, okeys_a, 37, first=300)
