@@ -56,10 +56,11 @@ def _traffic(shape, batch):
             rec = json.load(fh)
         if rec.get("sources") != KERNEL_SOURCES or _sources_sha() != rec["source_sha"]:
             continue
-        for name, v in rec.items():
-            if name.startswith("blind_rotate_kernel") and isinstance(v, dict) \
-                    and v.get("batch") == batch and shape == 0:
-                return v["hbm_bytes_per_launch"]
+        br = [v for name, v in rec.items()
+              if name.startswith("blind_rotate_kernel") and isinstance(v, dict)
+              and v.get("batch") == batch and shape == 0]
+        if br:  # the batch's own launch is the largest blind-rotation grid
+            return max(br, key=lambda v: v["grid"])["hbm_bytes_per_launch"]
     return None
 
 
@@ -83,7 +84,7 @@ def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path):
     also made (the largest copyBuffer dispatch)."""
     import csv
     import glob
-    from collections import Counter, defaultdict
+    from collections import defaultdict
 
     def per_dispatch(d, counter):
         path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
@@ -106,14 +107,15 @@ def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path):
     for name in fetch:
         if "copyBuffer" in name or name not in write:
             continue
-        # the dispatches of the timed batch: the most common grid size
-        grid = Counter(g for g, _ in fetch[name]).most_common(1)[0][0]
+        # the dispatches of the timed batch: the largest grid of the run (the
+        # unbatched latency measurement launches the same kernels smaller)
+        grid = max(g for g, _ in fetch[name])
         fk = [v for g, v in fetch[name] if g == grid]
         wk = [v for g, v in write[name] if g == grid]
         f_kib, w_kib = sum(fk) / len(fk), sum(wk) / len(wk)
         short = name.split("(")[0].split(" ")[-1].replace("fs::", "") if "<" not in name \
             else name.split("(")[0].replace("void ", "").replace("fs::", "").replace(" ", "")
-        rec[short] = {"batch": batch, "grid": grid, "dispatches": len(fk),
+        rec[short] = {"batch": batch, "grid": grid, "dispatches": len(fk),  # largest grid only
                       "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
                       "hbm_bytes_per_launch": int(1024 * (f_kib * rec["calibration"]["fetch_factor"]
                                                           + w_kib * rec["calibration"]["write_factor"]))}
