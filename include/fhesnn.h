@@ -156,10 +156,11 @@ FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
 /* Tuning of the blind-rotation kernel.  Every variant computes the same
  * bits; they differ in when the key slice of a digit row is requested
  * (before or after its forward transform) and in the register budget the
- * compiler was held to (waves per SIMD).  fs_br_variants() returns the
- * number of variants; fs_ctx_set_br_variant selects one for ring degree N
- * on this context (default 0).  The autotuner times them and picks. */
-FS_API int fs_br_variants(void);
+ * compiler was held to (waves per SIMD).  fs_br_variants(N) returns the
+ * number of variants for ring degree N (0 if N is not supported);
+ * fs_ctx_set_br_variant selects one for N on this context (default 0).
+ * The autotuner times them and picks. */
+FS_API int fs_br_variants(uint32_t N);
 FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
 
 /* Batches of at most max_jobs bootstrapping jobs (ciphertexts x program

@@ -410,7 +410,7 @@ int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs) {
   return ensure_ext(ctx, max_jobs * (size_t)(N + 1));
 }
 
-int fs_br_variants(void) { return blind_rotate_variants(); }
+int fs_br_variants(uint32_t N) { return blind_rotate_variants(N); }
 
 int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
   if (!ctx) return fail(FS_EINVAL, "null context");
@@ -423,7 +423,8 @@ int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
 int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant) {
   if (!ctx) return fail(FS_EINVAL, "null context");
   if (N != 1024 && N != 2048) return fail(FS_ENOTSUP, "ring degree without kernels");
-  if (variant < 0 || variant >= blind_rotate_variants()) return fail(FS_EINVAL, "no such kernel variant");
+  if (variant < 0 || variant >= blind_rotate_variants(N))
+    return fail(FS_EINVAL, "no such kernel variant");
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->br_variant[N] = variant;
   return FS_OK;

@@ -67,7 +67,7 @@ struct KsArgs {
 
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
                       const double* tw, hipStream_t st);
-int blind_rotate_variants();
+int blind_rotate_variants(uint32_t N);
 // split: two polynomial groups per job (small batches)
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
                         hipStream_t st);

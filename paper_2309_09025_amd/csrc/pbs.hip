@@ -541,7 +541,7 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // N = 1024: (0, 2), (1, 2), (2, 1), (2, 2); N = 2048: (0, 1), (2, 1), (1, 1),
 // (0, 2).  Split launches (two polynomial groups per job) use (1, 2) at
 // N = 1024 and (0, 1) at N = 2048.
-int blind_rotate_variants() { return 4; }
+int blind_rotate_variants(uint32_t N) { return N == 1024 || N == 2048 ? 4 : 0; }
 
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
                         hipStream_t st) {

@@ -78,7 +78,7 @@ SIGNATURES = {
     "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
     "fs_ctx_destroy": (_int, [_vp]),
     "fs_ctx_reserve": (_int, [_vp, _u32, _sz]),
-    "fs_br_variants": (_int, []),
+    "fs_br_variants": (_int, [_u32]),
     "fs_ctx_set_br_variant": (_int, [_vp, _u32, _int]),
     "fs_evk_upload": (_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     "fs_devkey_params": (_int, [_vp, _PP]),
@@ -273,8 +273,8 @@ class Context:
         _check("fs_ctx_set_br_variant", lib().fs_ctx_set_br_variant(self.h, N, variant))
 
 
-def br_variants() -> int:
-    return int(lib().fs_br_variants())
+def br_variants(N: int) -> int:
+    return int(lib().fs_br_variants(N))
 
 
 class DevKey:

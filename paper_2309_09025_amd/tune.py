@@ -69,7 +69,7 @@ def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
     lut = np.where(np.arange(P.p) < P.p // 2, 1, -1).astype(np.int32)
     stream = torch.cuda.current_stream()
     times = {}
-    for v in range(F.br_variants()):
+    for v in range(F.br_variants(P.N)):
         ctx.set_br_variant(P.N, v)
         F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)  # warm
         torch.cuda.synchronize()

@@ -66,7 +66,7 @@ def test_pbs_fire_bit_exact(gpu_env, okeys_a, keyswitch):
 def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
-    assert F.br_variants() == 4
+    assert F.br_variants(P.N) == 4
     m, ct = _pbs_inputs(P, sk, okeys_a, 8, first=200 + 8 * variant)
     f = O.lut_reset(P.p, 4, 2)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
@@ -85,6 +85,7 @@ def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
 def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, variant):
     ctx, get = gpu_env
     P, sk, evk, dk = get(1)
+    assert F.br_variants(P.N) == 4
     m, ct = _pbs_inputs(P, sk, okeys_b, 2, first=600 + 2 * variant)
     f = O.lut_fire(P.p, 4)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
