@@ -247,6 +247,33 @@ def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
             "pbs_per_s": round(cfg.pbs_count() / m, 1)}
 
 
+def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
+    """The paper's Poisson-encoded SNN on one image at a time (784 Sign
+    bootstrappings per step, FC 784->160 (LIF), FC 160->10 (LIF), T1 = 20)."""
+    import torch
+    cfg = synth.POISSON_SNN
+    _, W1, W2 = cfg.data()
+    net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
+    cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
+           for k in range(images + 1)]
+    net.run(cts[-1], cfg.thresholds(image_stream=images))  # warm (caches, graph)
+    torch.cuda.synchronize()
+    lat = []
+    for k in range(images):
+        thr = cfg.thresholds(image_stream=k)
+        t0 = time.perf_counter()
+        net.run(cts[k], thr)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    m = sum(lat) / len(lat)
+    return {"workload": "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
+                        "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "
+                        "spike-count scores, T1=20",
+            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
+            "bootstrappings_per_image": cfg.pbs_count(),
+            "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+
+
 def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):
     """64 images with T in {2..8} and hidden width 256 or 800, one launch per
     layer per timestep, one HIP graph per active set."""
@@ -487,6 +514,8 @@ def main():
         extra["single_image"] = single_image(F, NW, synth, ctx, dk, sk)
         _log("paper CSNN topology, single image")
         extra["paper_csnn"] = paper_csnn(F, NW, synth, ctx, dk, sk)
+        _log("Poisson-encoded SNN, single image")
+        extra["poisson_snn"] = poisson_snn(F, NW, synth, ctx, dk, sk)
         _log("uneven batch of 64 images")
         extra["uneven_batch"] = uneven_batch(F, NW, synth, ctx, dk, sk)
         _log("serving")
@@ -495,7 +524,7 @@ def main():
     # per prediction workload: the bootstrapping rate as a fraction of the
     # VALU roofline (same algorithmic count as the batched line), and the
     # oracle's time for the same work, extrapolated from its measured rate
-    for key in ("single_image", "paper_csnn", "uneven_batch"):
+    for key in ("single_image", "paper_csnn", "poisson_snn", "uneven_batch"):
         w = extra.get(key)
         if not w:
             continue

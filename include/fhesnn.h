@@ -201,6 +201,13 @@ FS_API int fs_lwe_conv2d(fs_ctx* ctx, const int32_t* W, uint32_t Ci, uint32_t H,
 FS_API int fs_lwe_add(fs_ctx* ctx, const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
                void* stream);
 
+/* Plaintext addition y = x + Delta c mod 2^32 on the body word of each
+ * ciphertext (a trivial encryption of c has zero mask, Sec. 4.1), Delta =
+ * 2^32 / p, p a power of two.  x, y: dev [count][dim] (y may alias x);
+ * c: dev int32 [count], one plaintext per row. */
+FS_API int fs_lwe_add_plain(fs_ctx* ctx, uint32_t p, const uint32_t* x, const int32_t* c,
+                            size_t count, uint32_t dim, uint32_t* y, void* stream);
+
 /* Programmable bootstrapping (Sec. 2.1: KeySwitch o Extract o BlindRotate
  * o Initialize) of B ciphertexts with one program function.
  * lut: host [p] residues, negacyclic (else FS_EINVAL).

@@ -490,6 +490,48 @@ def paper_csnn_run(keys: Keys, px_ct, Wc, W1, W2, geom, pool: int, vth: int, tau
     return I1, steps
 
 
+def add_plain_rows(p: int, ct, c):
+    """Row i plus the trivial encryption of c[i]: b += Delta c[i] (Sec. 4.1,
+    adding a plaintext to a ciphertext)."""
+    ct = np.array(ct, np.uint32, copy=True)
+    delta = (1 << 32) // p
+    c = np.asarray(c, np.int64)
+    ct[:, -1] = ((ct[:, -1].astype(np.int64) + delta * c) & 0xFFFFFFFF).astype(np.uint32)
+    return ct
+
+
+def poisson_spikes(keys: Keys, px_ct, m_t):
+    """Poisson coding on ciphertexts (Sec. 2.3: X = 1 iff X_o > M_t; Sec. 5.1:
+    one comparison = one Sign bootstrapping): LWE(q - m_t) through the Fire
+    function with threshold 1 (+1 if q - m_t >= 1, else -1), then +1 as in
+    Eq. FHE-Fire, giving LWE(2X)."""
+    P = keys.params
+    h = add_plain_rows(P.p, px_ct, -np.asarray(m_t, np.int64))
+    s = pbs(keys, test_poly(P.N, P.p, lut_fire(P.p, 1)), h, keyswitch=True)
+    return add_plain(P.p, s, 1)
+
+
+def poisson_snn_run(keys: Keys, px_ct, thresholds, W1, W2, vth: int, tau: int, T: int,
+                    nthreads=None):
+    """The Poisson-encoded SNN (Sec. 5.1, Table 1): per step the pixel spikes
+    of poisson_spikes, FC (LIF), FC (LIF), scores = the encrypted spike counts
+    of the output layer."""
+    w = np.asarray(px_ct).shape[1]
+    V1 = zero_ct(W1.shape[0], w)
+    V2 = zero_ct(W2.shape[0], w)
+    score = zero_ct(W2.shape[0], w)
+    steps = []
+    for t in range(T):
+        S0 = poisson_spikes(keys, px_ct, thresholds[t])
+        H1 = lwe_linear(W1, S0, add=V1)
+        S1, V1 = lif_step(keys, vth, tau, H1, nthreads)
+        H2 = lwe_linear(W2, S1, add=V2)
+        S2, V2 = lif_step(keys, vth, tau, H2, nthreads)
+        score = (score.astype(np.uint64) + S2).astype(np.uint32)
+        steps.append(dict(S0=S0, H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, score=score.copy()))
+    return steps
+
+
 # ---------------------------------------------------------------- plaintext SNN (mod p)
 
 def plain_lif_layer_run(p: int, I, vth: int, tau: int, T: int):
@@ -576,3 +618,25 @@ def plain_paper_csnn_run(p: int, px, Wc, W1, W2, geom, pool: int, vth: int, tau:
         steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, H3=H3, S3=S3, V3=V3,
                           score=score.copy()))
     return I1, steps
+
+
+def plain_poisson_snn_run(p: int, px, thresholds, W1, W2, vth: int, tau: int, T: int):
+    """poisson_snn_run on integers mod p: 2X = 2 [q > m_t]."""
+    px = np.asarray(px, np.int64)
+    W1 = np.asarray(W1, np.int64)
+    W2 = np.asarray(W2, np.int64)
+    V1 = np.zeros(W1.shape[0], np.int64)
+    V2 = np.zeros(W2.shape[0], np.int64)
+    score = np.zeros(W2.shape[0], np.int64)
+    steps = []
+    for t in range(T):
+        S0 = 2 * (px > np.asarray(thresholds[t], np.int64)).astype(np.int64)
+        H1 = (V1 + W1 @ S0) % p
+        S1 = plain_fire(p, vth, H1)
+        V1 = plain_reset(p, vth, tau, H1)
+        H2 = (V2 + W2 @ S1) % p
+        S2 = plain_fire(p, vth, H2)
+        V2 = plain_reset(p, vth, tau, H2)
+        score = (score + S2) % p
+        steps.append(dict(S0=S0, H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, score=score.copy()))
+    return steps

@@ -528,6 +528,17 @@ int fs_lwe_add(fs_ctx* ctx, const uint32_t* a, const uint32_t* b, size_t words, 
   return launch_rc(launch_lwe_add(a, b, words, y, as_stream(stream)), "lwe_add");
 }
 
+int fs_lwe_add_plain(fs_ctx* ctx, uint32_t p, const uint32_t* x, const int32_t* c, size_t count,
+                     uint32_t dim, uint32_t* y, void* stream) {
+  if (!ctx || (count && (!x || !c || !y))) return fail(FS_EINVAL, "fs_lwe_add_plain: null argument");
+  if (p < 2 || (p & (p - 1)) != 0) return fail(FS_EINVAL, "fs_lwe_add_plain: p must be a power of two");
+  if (dim == 0 || (count * dim) / 256 >= 0x7FFFFFFFull)
+    return fail(FS_EINVAL, "fs_lwe_add_plain: bad shape");
+  DeviceGuard g(ctx->device);
+  return launch_rc(launch_lwe_add_plain(x, c, delta_of(p), count, dim, y, as_stream(stream)),
+                   "lwe_add_plain");
+}
+
 int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const uint32_t* in, size_t B,
            uint32_t* out, int keyswitch, void* stream) {
   if (!ctx || !dk || !lut || (B && (!in || !out))) return fail(FS_EINVAL, "fs_pbs: null argument");

@@ -89,5 +89,7 @@ int launch_lwe_conv2d(const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd, ui
                       const uint32_t* x, const uint32_t* add, uint32_t* y, hipStream_t st);
 int launch_lwe_add(const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y,
                    hipStream_t st);
+int launch_lwe_add_plain(const uint32_t* x, const int32_t* c, uint32_t delta, size_t count,
+                         uint32_t dim, uint32_t* y, hipStream_t st);
 
 }  // namespace fs

@@ -77,6 +77,18 @@ lwe_add_kernel(const uint32_t* a, const uint32_t* b, size_t words, uint32_t* y) 
   if (i < words) y[i] = a[i] + b[i];
 }
 
+// y = x + (0, ..., 0, delta * c[row]): a plaintext added to each ciphertext
+// (its trivial encryption has zero mask), row by row.
+__global__ void __launch_bounds__(256)
+lwe_add_plain_kernel(const uint32_t* x, const int32_t* c, uint32_t delta, size_t count,
+                     uint32_t dim, uint32_t* y) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count * dim) return;
+  const size_t row = i / dim;
+  const uint32_t w = (uint32_t)(i - row * dim);
+  y[i] = x[i] + (w == dim - 1 ? delta * (uint32_t)c[row] : 0u);
+}
+
 #define FS_LAUNCH_CHECK()                 \
   do {                                    \
     hipError_t e_ = hipGetLastError();    \
@@ -107,6 +119,16 @@ int launch_lwe_add(const uint32_t* a, const uint32_t* b, size_t words, uint32_t*
                    hipStream_t st) {
   if (words == 0) return 0;
   lwe_add_kernel<<<dim3((uint32_t)((words + 255) / 256)), 256, 0, st>>>(a, b, words, y);
+  FS_LAUNCH_CHECK();
+  return 0;
+}
+
+int launch_lwe_add_plain(const uint32_t* x, const int32_t* c, uint32_t delta, size_t count,
+                         uint32_t dim, uint32_t* y, hipStream_t st) {
+  const size_t words = count * dim;
+  if (words == 0) return 0;
+  lwe_add_plain_kernel<<<dim3((uint32_t)((words + 255) / 256)), 256, 0, st>>>(x, c, delta, count,
+                                                                               dim, y);
   FS_LAUNCH_CHECK();
   return 0;
 }

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fs_lwe_conv2d": (_int, [_vp, _vp, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32,
                              _vp, _vp, _vp, _vp]),
     "fs_lwe_add": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    "fs_lwe_add_plain": (_int, [_vp, _u32, _vp, _vp, _sz, _u32, _vp, _vp]),
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
@@ -318,6 +319,15 @@ def lwe_conv2d(ctx: Context, W, x, y, Ci, H, Wd, stride, pad, add=None, stream=N
 def lwe_add(ctx: Context, a, b, y, stream=None):
     _check("fs_lwe_add", lib().fs_lwe_add(ctx.h, _dptr(a), _dptr(b), a.numel(), _dptr(y),
                                           _stream(stream)))
+    return y
+
+
+def lwe_add_plain(ctx: Context, p: int, x, c, y, stream=None):
+    """y = x + Delta c on the body word of each row; c: device int32 [rows]."""
+    import torch
+    assert c.dtype == torch.int32 and c.numel() == x.shape[0]
+    _check("fs_lwe_add_plain", lib().fs_lwe_add_plain(ctx.h, p, _dptr(x), _dptr(c), x.shape[0],
+                                                      x.shape[1], _dptr(y), _stream(stream)))
     return y
 
 

@@ -229,6 +229,73 @@ class PaperCSNN:
         return F.to_host(self.score), steps
 
 
+class PoissonSNN:
+    """The paper's Poisson-encoded SNN on one encrypted 4-bit image (Sec. 2.3,
+    Sec. 5.1): every step each pixel ciphertext LWE(q) gets the plaintext
+    -m_t of that step's threshold matrix added and goes through the Fire
+    function with threshold 1 (one Sign bootstrapping), +1 afterwards, which
+    gives LWE(2 [q > m_t]); then FC (LIF) -> FC (LIF), output spikes counted.
+    The thresholds are inputs (the server's public randomness).  Each
+    timestep is one HIP graph; the step's threshold row is copied into a
+    fixed buffer before the replay."""
+
+    def __init__(self, ctx, dk, W1, W2, lif: LifSpec = LifSpec(), capture: bool = True):
+        self.ctx, self.dk, self.lif = ctx, dk, lif
+        P = dk.params
+        self.p = P.p
+        self.width = w = P.n + 1
+        self.pixels = W1.shape[1]
+        self.hidden, self.classes = W1.shape[0], W2.shape[0]
+        self.W1 = F.to_device(np.ascontiguousarray(W1, np.int32))
+        self.W2 = F.to_device(np.ascontiguousarray(W2, np.int32))
+        self.fire1, _ = F.lif_luts(1, 0, P.p)  # +1 iff q - m_t >= 1
+        self.px = _zeros(self.pixels, w)
+        self.neg_thr = torch.zeros(self.pixels, dtype=torch.int32, device="cuda")
+        self.ones = torch.ones(self.pixels, dtype=torch.int32, device="cuda")
+        self.H0, self.S0 = _zeros(self.pixels, w), _zeros(self.pixels, w)
+        self.H1, self.V1, self.S1 = (_zeros(self.hidden, w) for _ in range(3))
+        self.H2, self.V2, self.S2 = (_zeros(self.classes, w) for _ in range(3))
+        self.score = _zeros(self.classes, w)
+        self.capture = capture
+        self.graph = None
+        self.pbs_count = 0
+        ctx.reserve(P.N, max(self.pixels, 2 * self.hidden))
+
+    def _step(self):
+        c, dk, L = self.ctx, self.dk, self.lif
+        F.lwe_add_plain(c, self.p, self.px, self.neg_thr, self.H0)
+        F.pbs(c, dk, self.fire1, self.H0, self.S0, keyswitch=True)
+        F.lwe_add_plain(c, self.p, self.S0, self.ones, self.S0)
+        F.lwe_linear(c, self.W1, self.S0, self.H1, add=self.V1)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        F.lwe_linear(c, self.W2, self.S1, self.H2, add=self.V2)
+        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        F.lwe_add(c, self.score, self.S2, self.score)
+
+    def run(self, px_ct, thresholds, record: bool = False):
+        """px_ct: device [pixels][n+1]; thresholds: host [T][pixels] in [0, p).
+        Returns the encrypted spike counts (host) and, if record, per-step host
+        copies of every state buffer."""
+        T = len(thresholds)
+        self.px.copy_(px_ct)
+        neg = torch.from_numpy(-np.ascontiguousarray(thresholds, np.int32)).to("cuda")
+        for b in (self.V1, self.V2, self.score):
+            b.zero_()
+        if self.graph is None:
+            self.graph = StepGraph(self._step, self.capture)
+        steps = []
+        for t in range(T):
+            self.neg_thr.copy_(neg[t])
+            self.graph.run()
+            self.pbs_count += self.pixels + 2 * (self.hidden + self.classes)
+            if record:
+                torch.cuda.synchronize()
+                steps.append({k: F.to_host(getattr(self, k)) for k in
+                              ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score")})
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
+
 def pbs_count_paper_csnn(T: int) -> int:
     """Bootstrappings per image of the paper's CSNN (Table 1): 2 per LIF
     neuron per step over the 10x12x12, 160 and 10 LIF neurons."""

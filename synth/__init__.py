@@ -186,6 +186,50 @@ PAPER_CSNN = PaperCSNN()
 PAPER_CSNN_MINI = PaperCSNN(H=8, Wd=8, Co=2, K=4, stride=2, pad=1, hidden=6, classes=3, T=2)
 
 
+@dataclass(frozen=True)
+class PoissonSNN:
+    """The paper's Poisson-encoded SNN (Sec. 2.3 Poisson coding; Sec. 5.1,
+    Table 1): every step each pixel spikes when it exceeds a fresh uniform
+    threshold, then FC (LIF) -> FC (LIF) with the output spikes counted.
+    Pixels are 4-bit (q = pixel >> 4) and the thresholds m_t uniform in
+    [0, 15] on the same scale; weights in [w_lo, w_hi]."""
+    H: int = 28
+    Wd: int = 28
+    hidden: int = 160
+    classes: int = 10
+    w_lo: int = -8
+    w_hi: int = 8
+    vth: int = 4
+    tau: int = 2
+    T: int = 20
+
+    @property
+    def pixels(self):
+        return self.H * self.Wd
+
+    def pbs_count(self) -> int:
+        """One Sign bootstrapping per pixel and two per LIF neuron, per step."""
+        return (self.pixels + 2 * self.hidden + 2 * self.classes) * self.T
+
+    def data(self, seed: int = SEED_DATA, image_stream: int = 0):
+        if self.H == 28 and self.Wd == 28:
+            px = quantise_pixels(image_like_digit(seed, image_stream))
+        else:
+            px = uniform_int(seed, self.pixels, 0, 15, stream=30 + image_stream)
+        W1 = uniform_int(seed, (self.hidden, self.pixels), self.w_lo, self.w_hi, stream=16)
+        W2 = uniform_int(seed, (self.classes, self.hidden), self.w_lo, self.w_hi, stream=17)
+        return px, W1, W2
+
+    def thresholds(self, seed: int = SEED_DATA, image_stream: int = 0):
+        """The uniform matrices M_t of Poisson coding, [T][pixels] in [0, 15]."""
+        return uniform_int(seed, (self.T, self.pixels), 0, 15, stream=40 + image_stream)
+
+
+POISSON_SNN = PoissonSNN()
+# a small instance the oracle runs end to end
+POISSON_SNN_MINI = PoissonSNN(H=4, Wd=4, hidden=5, classes=3, T=3)
+
+
 def uneven_batch(seed: int = SEED_DATA, images: int = 64):
     """Per-image timestep counts in {2..8} and hidden widths in {256, 800}."""
     g = rng(seed, 77)

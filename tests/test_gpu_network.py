@@ -177,3 +177,61 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
     total = sum(steps[t]["S3"].astype(np.uint64) for t in range(cfg.T)) & 0xFFFFFFFF
     assert np.array_equal(score, total.astype(np.uint32))
 
+
+@pytest.mark.parametrize("capture", [False, True])
+def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, capture):
+    """The Poisson-encoded SNN (per step: per-pixel plaintext threshold, one
+    Sign bootstrapping per pixel, FC (LIF), FC (LIF), spike counts) at a size
+    the oracle runs end to end, eager and replayed from a HIP graph."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.POISSON_SNN_MINI
+    px, W1, W2 = cfg.data()
+    thr = cfg.thresholds()
+    net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), capture=capture)
+    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
+    assert net.pbs_count == cfg.pbs_count()
+    osteps = O.poisson_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
+                               thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        for k in ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert np.array_equal(steps[t][k], osteps[t][k]), (t, k)
+    assert np.array_equal(score, osteps[-1]["score"])
+
+
+def test_poisson_snn_full_size_sampled(gpu_env, okeys_a):
+    """Full size (784 pixels, FC 784->160, FC 160->10, T1 = 20, Table 1's
+    (784 + 2 x 160 + 2 x 10) T1 bootstrappings): the oracle recomputes the
+    Sign bootstrapping of sampled pixels at every step; every spike of every
+    step decrypts to the plaintext coding; the layers are checked as linear
+    maps of the GPU's own spikes."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.POISSON_SNN
+    px, W1, W2 = cfg.data()
+    thr = cfg.thresholds()
+    net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
+    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
+    assert net.pbs_count == cfg.pbs_count() == (784 + 2 * 160 + 2 * 10) * cfg.T
+    octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
+    sample = [0, 300, 404, 783]
+    plain = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    wrong = 0
+    for t in range(cfg.T):
+        if t % 5 == 0:
+            want = O.poisson_spikes(okeys_a, octs[sample], thr[t][sample])
+            assert np.array_equal(steps[t]["S0"][sample], want), t
+        dec = F.decrypt(sk, steps[t]["S0"])
+        assert set(np.unique(dec)) <= {0, 2}, t
+        wrong += int((dec != O.centred(P.p, plain[t]["S0"])).sum())
+    # each decryption of a bootstrapped output fails with probability ~9e-6
+    # (4.45 sigma): 0.14 failures are expected among the 15,680 spikes
+    assert wrong <= 3, wrong
+    for t in range(cfg.T):
+        V1prev = steps[t - 1]["V1"] if t else O.zero_ct(cfg.hidden, P.n + 1)
+        assert np.array_equal(steps[t]["H1"], O.lwe_linear(W1, steps[t]["S0"], add=V1prev)), t
+        V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.classes, P.n + 1)
+        assert np.array_equal(steps[t]["H2"], O.lwe_linear(W2, steps[t]["S1"], add=V2prev)), t
+        for k in ("S1", "S2"):
+            assert set(np.unique(F.decrypt(sk, steps[t][k]))) <= {0, 2}, (t, k)
+

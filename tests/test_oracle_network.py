@@ -68,3 +68,42 @@ def test_paper_csnn_oracle_first_layer_equals_plaintext(okeys_a):
         V3prev = steps[t - 1]["V3"] if t else O.zero_ct(cfg.classes, P.n + 1)
         assert np.array_equal(steps[t]["H3"], O.lwe_linear(W2, steps[t]["S2"], add=V3prev))
 
+
+def test_poisson_counts_match_table_1():
+    """Table 1: (784 + 2 x 160 + 2 x 10) T1 bootstrappings per image."""
+    c = synth.POISSON_SNN
+    assert c.pbs_count() == (784 + 2 * 160 + 2 * 10) * c.T
+
+
+def test_add_plain_rows_adds_each_rows_plaintext(okeys_a):
+    """A per-row plaintext added to ciphertexts decrypts to the sums mod p."""
+    P = O.SHAPE_A
+    m = synth.uniform_int(synth.SEED_DATA, 40, -15, 16, stream=71)
+    c = synth.uniform_int(synth.SEED_DATA, 40, -40, 40, stream=72)
+    ct = O.encrypt(P, okeys_a.s, m, synth.SEED_ENC, 9000)
+    got = O.decrypt(P.p, okeys_a.s, O.add_plain_rows(P.p, ct, c))
+    assert np.array_equal(got, O.centred(P.p, m.astype(np.int64) + c))
+
+
+def test_poisson_snn_oracle_spikes_equal_plaintext(okeys_a):
+    """Poisson coding on ciphertexts (Sec. 2.3: X = 1 iff pixel > threshold,
+    as one Sign bootstrapping) decrypts to 2X of the plaintext coding at every
+    step, and each layer's input is the WeightSum of the previous layer's
+    spikes plus V (Theorem 3.1).  The LIF layers' decryptions are not pinned:
+    their inputs sum 16 bootstrapped spikes with weights up to 8."""
+    P = O.SHAPE_A
+    cfg = synth.PoissonSNN(H=4, Wd=4, hidden=4, classes=2, T=3)
+    px, W1, W2 = cfg.data()
+    thr = cfg.thresholds()
+    ct = O.encrypt(P, okeys_a.s, px, synth.SEED_ENC)
+    steps = O.poisson_snn_run(okeys_a, ct, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    psteps = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        assert np.array_equal(O.decrypt(P.p, okeys_a.s, steps[t]["S0"]),
+                              O.centred(P.p, psteps[t]["S0"])), t
+        V1prev = steps[t - 1]["V1"] if t else O.zero_ct(cfg.hidden, P.n + 1)
+        assert np.array_equal(steps[t]["H1"], O.lwe_linear(W1, steps[t]["S0"], add=V1prev))
+        V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.classes, P.n + 1)
+        assert np.array_equal(steps[t]["H2"], O.lwe_linear(W2, steps[t]["S1"], add=V2prev))
+    assert any(psteps[t]["S0"].any() for t in range(cfg.T))  # some pixel spiked
+
