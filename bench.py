@@ -219,6 +219,34 @@ def tiny_lif(F, NW, synth, ctx, dk, sk, reps=5):
             "pbs_per_s": round(2 * 32 * cfg.T / m, 1)}
 
 
+def lif_orders(F, synth, ctx, dk, sk, neurons=2048, reps=3):
+    """One LIF activation of 2048 neurons (4096 blind rotations) in the two
+    orders: key switch after each rotation (fs_pbs_lif, 4096 key switches,
+    outputs under s) and key switch first (fs_pbs_lif_ks_first, 2048 key
+    switches, outputs under z with blind-rotation noise only)."""
+    import torch
+    P = dk.params
+    m = synth.messages(synth.SEED_DATA, neurons, P.p, stream=91)
+    out = {}
+    for name, enc, width, fn in (("ks_after", F.encrypt, P.n + 1, F.pbs_lif),
+                                 ("ks_first", F.encrypt_z, P.N + 1, F.pbs_lif_ks_first)):
+        h = F.to_device(enc(sk, m, synth.SEED_ENC, 70000))
+        s2 = torch.zeros((neurons, width), dtype=torch.int32, device="cuda")
+        vv = torch.zeros_like(s2)
+        fn(ctx, dk, 4, 2, h, s2, vv)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn(ctx, dk, 4, 2, h, s2, vv)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        out[name] = {"ms": round(ms, 3), "pbs_per_s": round(2 * neurons / ms * 1e3, 1),
+                     "output_words": width}
+    out["workload"] = (f"one LIF activation of {neurons} neurons (Fire + Reset = "
+                       f"{2 * neurons} blind rotations), N={P.N}")
+    return out
+
+
 def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
     """The paper's CSNN topology on one image at a time (conv 10x8x8 s2 p1
     (LIF) -> 2x2 pool folded into FC 360->160 (LIF) -> FC 160->10 (LIF),
@@ -510,6 +538,8 @@ def main():
         from paper_2309_09025_amd import serve as SV
         _log("tiny LIF layer")
         extra["tiny_lif"] = tiny_lif(F, NW, synth, ctx, dk, sk)
+        _log("LIF activation, key switch after vs first")
+        extra["lif_orders"] = lif_orders(F, synth, ctx, dk, sk)
         _log("single-image conv SNN")
         extra["single_image"] = single_image(F, NW, synth, ctx, dk, sk)
         _log("paper CSNN topology, single image")

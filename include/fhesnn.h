@@ -106,6 +106,14 @@ FS_API int fs_keygen(const fs_params* params, uint64_t seed, fs_secret** sk, fs_
 FS_API int fs_encrypt(const fs_secret* sk, const int32_t* m, size_t count, uint64_t seed,
                uint64_t first_index, uint32_t* ct_out);
 
+/* The same encryption under the extracted key z (Sec. 2.1, LWE item, with
+ * the RLWE secret's coefficients as the LWE key): ct_out: host [count][N+1].
+ * Input for the key-switch-first ordering (fs_pbs_lif_ks_first), where the
+ * ciphertexts between bootstrappings live under z.  Stream objects are
+ * shared with fs_encrypt: use distinct first_index ranges for the two. */
+FS_API int fs_encrypt_z(const fs_secret* sk, const int32_t* m, size_t count, uint64_t seed,
+                        uint64_t first_index, uint32_t* ct_out);
+
 /* Decryption (Sec. 2.1): m = round((b - <a,key>) p / 2^32) mod p, centred.
  * dim = n+1 decrypts under s; dim = N+1 under z (extracted samples).
  * ct: host [count][dim]; m_out: host [count]. */
@@ -223,6 +231,19 @@ FS_API int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const ui
  * the Fire function.  h, spike2_out, v_out: dev [B][n+1]; v_out may alias h. */
 FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
                uint32_t* spike2_out, uint32_t* v_out, void* stream);
+
+/* The LIF activation in the key-switch-first order (the bootstrapping of
+ * Sec. 2.1 with its Key Switching step moved in front of the Blind
+ * Rotation): LWE_z(H) is key-switched to LWE_s(H) once, then blind-rotated
+ * with the Fire and Reset functions and extracted, so the outputs stay
+ * under z and carry the blind-rotation noise only (no key-switch noise),
+ * and one key switch serves both functions.
+ * h, spike2_out, v_out: dev [B][N+1] under z; spike2_out = LWE(2S),
+ * v_out = LWE(V') as in fs_pbs_lif.  Either output may alias h; the two
+ * outputs may not alias each other.  Uses the context's scratch. */
+FS_API int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif,
+                               const uint32_t* h, size_t B, uint32_t* spike2_out,
+                               uint32_t* v_out, void* stream);
 
 /* One contiguous range of LIF neurons of one client for fs_pbs_lif_ranges:
  * its evaluation key and its h / spike2_out / v_out rows (as in

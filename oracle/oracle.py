@@ -203,6 +203,12 @@ def encrypt(P: Params, s, m, seed: int, first_index: int = 0):
     return ct
 
 
+def encrypt_z(P: Params, z, m, seed: int, first_index: int = 0):
+    """The same LWE encryption with the RLWE secret z as the key (dimension
+    N): the form of the samples that sample extraction produces."""
+    return encrypt(replace(P, n=P.N), z, m, seed, first_index)
+
+
 def decrypt(p: int, key, ct):
     ct = _c(np.atleast_2d(ct), np.uint32)
     key = _c(key, np.int32)
@@ -370,6 +376,18 @@ def lif_step(keys: Keys, vth: int, tau: int, h, nthreads=None):
     return spikes, both[1]
 
 
+def lif_step_ks_first(keys: Keys, vth: int, tau: int, h_z, nthreads=None):
+    """The LIF activation with the bootstrapping's steps reordered (Sec. 2.1:
+    Key Switching moved in front of the Blind Rotation): LWE_z(H) is
+    key-switched to LWE_s(H), which both functions then bootstrap without a
+    key switch; returns (LWE_z(2S), LWE_z(V'))."""
+    P = keys.params
+    vf, vr = lif_test_polys(P, vth, tau)
+    hs = keyswitch(keys, _c(np.atleast_2d(h_z), np.uint32))
+    spikes = add_plain(P.p, pbs(keys, vf, hs, keyswitch=False, nthreads=nthreads), 1)
+    return spikes, pbs(keys, vr, hs, keyswitch=False, nthreads=nthreads)
+
+
 def pbs_two(keys, v0, v1, h, nthreads=None):
     """Bootstrap every row of h with two test polynomials (one thread pool)."""
     P = keys.params
@@ -412,15 +430,18 @@ def zero_ct(count: int, dim1: int):
     return np.zeros((count, dim1), np.uint32)
 
 
-def lif_layer_run(keys: Keys, I_ct, vth: int, tau: int, T: int, nthreads=None):
+def lif_layer_run(keys: Keys, I_ct, vth: int, tau: int, T: int, nthreads=None,
+                  ks_first: bool = False):
     """One LIF layer driven by a static input current LWE(I) for T steps:
     H[t] = V[t-1] + I; (2S[t], V[t]) = (FHE-Fire(H) + 1, FHE-Reset(H)).
-    Returns lists (per step) of H, 2S and V ciphertexts."""
+    Returns lists (per step) of H, 2S and V ciphertexts.  ks_first: the
+    ciphertexts are under z and each step uses lif_step_ks_first."""
+    step = lif_step_ks_first if ks_first else lif_step
     V = zero_ct(I_ct.shape[0], I_ct.shape[1])
     Hs, Ss, Vs = [], [], []
     for _ in range(T):
         H = (V + I_ct).astype(np.uint32)
-        S2, V = lif_step(keys, vth, tau, H, nthreads)
+        S2, V = step(keys, vth, tau, H, nthreads)
         Hs.append(H); Ss.append(S2); Vs.append(V)
     return Hs, Ss, Vs
 

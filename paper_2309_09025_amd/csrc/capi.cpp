@@ -315,6 +315,13 @@ int fs_encrypt(const fs_secret* sk, const int32_t* m, size_t count, uint64_t see
   return FS_OK;
 }
 
+int fs_encrypt_z(const fs_secret* sk, const int32_t* m, size_t count, uint64_t seed,
+                 uint64_t first_index, uint32_t* ct_out) {
+  if (!sk || (count && (!m || !ct_out))) return fail(FS_EINVAL, "fs_encrypt_z: null argument");
+  encrypt(*sk, m, count, seed, first_index, ct_out, true);
+  return FS_OK;
+}
+
 int fs_decrypt(const fs_secret* sk, const uint32_t* ct, size_t count, uint32_t dim,
                int32_t* m_out) {
   if (!sk || (count && (!ct || !m_out))) return fail(FS_EINVAL, "fs_decrypt: null argument");
@@ -572,6 +579,66 @@ int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32
   if (rc) return rc;
   const uint32_t add[2] = {delta_of(p), 0u};  // 2S = bootstrap_Fire + 1
   return run_pbs(ctx, dk, tp, 2, h, B, spike2_out, v_out, add, 1, as_stream(stream));
+}
+
+int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h,
+                        size_t B, uint32_t* spike2_out, uint32_t* v_out, void* stream) {
+  if (!ctx || !dk || !lif || (B && (!h || !spike2_out || !v_out)))
+    return fail(FS_EINVAL, "fs_pbs_lif_ks_first: null argument");
+  if (dk->device != ctx->device)
+    return fail(FS_EPARAM, "fs_pbs_lif_ks_first: key lives on another device");
+  if (B > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ks_first: batch too large");
+  if (spike2_out == v_out) return fail(FS_EINVAL, "fs_pbs_lif_ks_first: the two outputs alias");
+  const fs_params& P = dk->prm;
+  std::vector<int32_t> fire(P.p), reset(P.p);
+  int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
+  if (rc) return rc;
+  rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
+  if (rc) return rc;
+  if (B == 0) return FS_OK;
+  hipStream_t st = as_stream(stream);
+  // LWE_z(H) -> LWE_s(H), once per neuron: both functions bootstrap it
+  rc = ensure_ext(ctx, B * (size_t)(P.n + 1));
+  if (rc) return rc;
+  KsArgs ks{};
+  ks.in = h;
+  ks.ksk = dk->ksk;
+  ks.kskp = dk->kskp;
+  ks.out0 = ctx->ext;
+  ks.nlut = 1;
+  ks.n = P.n;
+  ks.N = P.N;
+  ks.t = P.ks_t;
+  ks.beta = P.ks_base_bit;
+  rc = launch_rc(launch_keyswitch(ks, B, st), "key switch");
+  if (rc) return rc;
+  // Fire and Reset blind rotations, extracted straight into the outputs
+  const size_t jobs = 2 * B;
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  BrArgs br{};
+  br.in = ctx->ext;
+  br.tpoly0 = tp[0];
+  br.tpoly1 = tp[1];
+  br.nlut = 2;
+  br.n = P.n;
+  br.bsk = dk->bsk;
+  br.fwd_tw = dk->fwd_tw;
+  br.inv_tw = dk->inv_tw;
+  br.post = dk->post;
+  br.uni = dk->uni;
+  br.out0 = spike2_out;
+  br.out1 = v_out;
+  br.plain_b[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
+  br.plain_b[1] = 0u;
+  return launch_rc(
+      launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, st),
+      "blind rotation");
 }
 
 int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,

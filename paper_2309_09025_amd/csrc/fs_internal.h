@@ -58,7 +58,7 @@ enum Domain : uint32_t {
 
 int keygen(const fs_params& prm, uint64_t seed, Secret** sk, EvalKey** evk);
 void encrypt(const Secret& sk, const int32_t* m, size_t count, uint64_t seed, uint64_t first,
-             uint32_t* ct);
+             uint32_t* ct, bool under_z = false);
 int decrypt(const Secret& sk, const uint32_t* ct, size_t count, uint32_t dim, int32_t* m);
 int test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v);
 void lif_luts(const fs_lif& lif, uint32_t p, int32_t* fire, int32_t* reset);

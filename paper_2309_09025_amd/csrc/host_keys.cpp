@@ -175,15 +175,16 @@ int keygen(const fs_params& prm, uint64_t seed, Secret** sk_out, EvalKey** evk_o
 }
 
 void encrypt(const Secret& sk, const int32_t* m, size_t count, uint64_t seed, uint64_t first,
-             uint32_t* ct) {
-  const uint32_t n = sk.prm.n, p = sk.prm.p, delta = delta_of(p);
+             uint32_t* ct, bool under_z) {
+  const uint32_t n = under_z ? sk.prm.N : sk.prm.n, p = sk.prm.p, delta = delta_of(p);
+  const int32_t* key = under_z ? sk.z.data() : sk.s.data();
   for (size_t k = 0; k < count; ++k) {
     uint32_t* c = ct + k * (size_t)(n + 1);
     ChaChaStream ca(seed, kDomEncA, first + k);
     uint32_t dot = 0;
     for (uint32_t i = 0; i < n; ++i) {
       c[i] = ca.word(i);
-      dot += c[i] * (uint32_t)sk.s[i];
+      dot += c[i] * (uint32_t)key[i];
     }
     ChaChaStream ce(seed, kDomEncE, first + k);
     const uint32_t e = torus_gaussian(ce.word(0), ce.word(1), sk.prm.sigma_lwe);

@@ -43,6 +43,12 @@ struct BrArgs {
   const double* inv_tw;   // [N/2] omega^{-e}
   const double* post;     // [N] psi^{-j} N^{-1}
   uint32_t* ext;          // [jobs][N+1] extracted samples under z
+  // routed extraction (single-key launches): when out0 is set, job j's
+  // sample goes to row j / nlut of out0 (function 0) or out1 (function 1)
+  // with plain_b[j % nlut] added to its body, instead of to ext
+  uint32_t* out0;
+  uint32_t* out1;
+  uint32_t plain_b[2];
   UniTw uni;              // roots shared by all threads (scalar operands)
   // multi-key launch: per-range inputs and keys (in and bsk unused)
   const JobRange* ranges;

@@ -243,14 +243,22 @@ blind_rotate_kernel(BrArgs a) {
   if constexpr (W == 2) __syncthreads();  // the extraction reads both accumulators
 
   // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
-  uint32_t* out = a.ext + job * (size_t)(N + 1);
+  uint32_t* out;
+  uint32_t plain = 0u;
+  if (a.out0) {
+    const uint32_t lut = (uint32_t)(job % a.nlut);
+    out = (lut == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
+    plain = a.plain_b[lut];
+  } else {
+    out = a.ext + job * (size_t)(N + 1);
+  }
   const int tid = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < 16 / W; ++r) {
     const int j = tid + W * TP * r;
     out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
   }
-  if (tid == 0) out[N] = acc[1][0];
+  if (tid == 0) out[N] = acc[1][0] + plain;
 }
 
 // ---------------------------------------------------------------------------

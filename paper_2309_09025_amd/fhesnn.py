@@ -65,6 +65,7 @@ SIGNATURES = {
     "fs_params_default": (_int, [_int, _PP]),
     "fs_keygen": (_int, [_PP, _u64, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "fs_encrypt": (_int, [_vp, _i32p, _sz, _u64, _u64, _u32p]),
+    "fs_encrypt_z": (_int, [_vp, _i32p, _sz, _u64, _u64, _u32p]),
     "fs_decrypt": (_int, [_vp, _u32p, _sz, _u32, _i32p]),
     "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
     "fs_ctx_set_split": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -91,6 +92,7 @@ SIGNATURES = {
     "fs_lwe_add_plain": (_int, [_vp, _u32, _vp, _vp, _sz, _u32, _vp, _vp]),
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
+    "fs_pbs_lif_ks_first": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "fs_ntt_polymul": (_int, [_vp, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
@@ -208,6 +210,15 @@ def encrypt(sk: Secret, m, seed: int, first_index: int = 0) -> np.ndarray:
     ct = np.zeros((m.size, sk.params.n + 1), np.uint32)
     _check("fs_encrypt", lib().fs_encrypt(sk.h, mp, m.size, seed, first_index,
                                           ct.ctypes.data_as(_u32p)))
+    return ct
+
+
+def encrypt_z(sk: Secret, m, seed: int, first_index: int = 0) -> np.ndarray:
+    """Encryption under the extracted key z: [count][N+1]."""
+    m, mp = _np_i32(np.atleast_1d(m))
+    ct = np.zeros((m.size, sk.params.N + 1), np.uint32)
+    _check("fs_encrypt_z", lib().fs_encrypt_z(sk.h, mp, m.size, seed, first_index,
+                                              ct.ctypes.data_as(_u32p)))
     return ct
 
 
@@ -342,6 +353,20 @@ def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
     lif = CLif(v_th, tau)
     _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
                                           _dptr(spike2_out), _dptr(v_out), _stream(stream)))
+
+
+def pbs_lif_ks_first(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
+                     stream=None):
+    """Key switch first, then Fire and Reset: h, spike2_out, v_out are
+    [B][N+1] under z."""
+    w = dk.params.N + 1
+    for name, t in (("h", h), ("spike2_out", spike2_out), ("v_out", v_out)):
+        if t.dim() != 2 or t.shape[1] != w or t.shape[0] != h.shape[0]:
+            raise ValueError(f"pbs_lif_ks_first: {name} must be [{h.shape[0]}][{w}]")
+    lif = CLif(v_th, tau)
+    _check("fs_pbs_lif_ks_first",
+           lib().fs_pbs_lif_ks_first(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
+                                     _dptr(spike2_out), _dptr(v_out), _stream(stream)))
 
 
 def pbs_lif_ranges(ctx: Context, v_th: int, tau: int, ranges, stream=None):

@@ -61,12 +61,17 @@ class StepGraph:
 
 
 class LifLayerNet:
-    """One LIF layer fed by a static current I = W x (the tiny LIF workload)."""
+    """One LIF layer fed by a static current I = W x (the tiny LIF workload).
 
-    def __init__(self, ctx, dk, W: np.ndarray, lif: LifSpec = LifSpec(), capture: bool = False):
+    ks_first: the key-switch-first order (fs_pbs_lif_ks_first); inputs and
+    states are then ciphertexts under z, [.][N+1]."""
+
+    def __init__(self, ctx, dk, W: np.ndarray, lif: LifSpec = LifSpec(), capture: bool = False,
+                 ks_first: bool = False):
         self.ctx, self.dk, self.lif = ctx, dk, lif
         P = dk.params
-        self.width = P.n + 1
+        self.ks_first = ks_first
+        self.width = (P.N if ks_first else P.n) + 1
         self.W = F.to_device(np.ascontiguousarray(W, np.int32))
         self.O = W.shape[0]
         self.I = _zeros(self.O, self.width)
@@ -80,10 +85,13 @@ class LifLayerNet:
 
     def _step(self):
         F.lwe_add(self.ctx, self.V, self.I, self.H)
-        F.pbs_lif(self.ctx, self.dk, self.lif.v_th, self.lif.tau, self.H, self.S, self.V)
+        act = F.pbs_lif_ks_first if self.ks_first else F.pbs_lif
+        act(self.ctx, self.dk, self.lif.v_th, self.lif.tau, self.H, self.S, self.V)
 
     def run(self, x_ct: torch.Tensor, T: int, record: bool = True):
-        """x_ct: device [inputs][n+1].  Returns per-step host copies (H, 2S, V)."""
+        """x_ct: device [inputs][width].  Returns per-step host copies (H, 2S, V)."""
+        if x_ct.shape[1] != self.width:
+            raise ValueError(f"inputs must be [inputs][{self.width}] ciphertexts")
         F.lwe_linear(self.ctx, self.W, x_ct, self.I)
         self.V.zero_()
         if self.graph is None:  # the step reads and writes the same buffers for every input

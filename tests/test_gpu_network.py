@@ -34,6 +34,29 @@ def test_tiny_lif_layer_bit_exact_and_spike_for_spike(gpu_env, okeys_a, capture)
 
 
 @pytest.mark.parametrize("capture", [False, True])
+def test_tiny_lif_layer_key_switch_first_bit_exact(gpu_env, okeys_a, capture):
+    """The tiny LIF layer in the key-switch-first order: inputs encrypted
+    under z, states [.][N+1], one key switch per neuron per step."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.TinyLIF()
+    x, W = cfg.data()
+    ct = F.encrypt_z(sk, x, synth.SEED_ENC)
+    net = NW.LifLayerNet(ctx, dk, W, NW.LifSpec(cfg.vth, cfg.tau), capture=capture,
+                         ks_first=True)
+    got = net.run(F.to_device(ct), cfg.T)
+    I_ct = O.lwe_linear(W, O.encrypt_z(O.SHAPE_A, okeys_a.z, x, synth.SEED_ENC))
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I_ct, cfg.vth, cfg.tau, cfg.T, ks_first=True)
+    pH, pS, pV = O.plain_lif_layer_run(P.p, W.astype(np.int64) @ x, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        H, S, V = got[t]
+        assert S.shape == (cfg.neurons, P.N + 1)
+        assert np.array_equal(H, Hs[t]) and np.array_equal(S, Ss[t]) and np.array_equal(V, Vs[t]), t
+        assert np.array_equal(F.decrypt(sk, S), O.centred(P.p, pS[t])), t
+        assert np.array_equal(F.decrypt(sk, V), O.centred(P.p, pV[t])), t
+
+
+@pytest.mark.parametrize("capture", [False, True])
 def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, capture):
     """The conv -> FC -> FC topology at a size the oracle runs end to end."""
     ctx, get = gpu_env

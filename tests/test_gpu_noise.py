@@ -139,6 +139,46 @@ def test_output_noise_matches_the_error_model(gpu_env):
     assert 1 - half - 0.10 < var / var_pred < 1 + half + 0.10
 
 
+def test_key_switch_first_outputs_carry_blind_rotation_noise_only(gpu_env):
+    """Key-switch-first LIF activation on every message x 32 (1024 neurons,
+    2048 blind rotations): outputs under z decrypt to Fire + 1 and Reset,
+    and the spike outputs' error variance is the blind rotation's alone
+    (model std 2^-8.85 against 2^-8.15 with the key switch after it).  A
+    wrong decryption is accepted only for a neuron whose key-switched input
+    lies within 5 mod-switch standard deviations of its window edge."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m = np.tile(np.arange(P.p, dtype=np.int32) - P.p // 2 + 1, 32)
+    h = F.encrypt_z(sk, m, synth.SEED_ENC, 300000)
+    s2 = torch.zeros((m.size, P.N + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    hd = F.to_device(h)
+    F.pbs_lif_ks_first(ctx, dk, 4, 2, hd, s2, vv)
+    hs = torch.zeros((m.size, P.n + 1), dtype=torch.int32, device="cuda")
+    F.keyswitch(ctx, dk, hd, hs)  # the same key-switched input, for the error check
+    torch.cuda.synchronize()
+    got_s, got_v, got_h = F.to_host(s2), F.to_host(vv), F.to_host(hs)
+    s, z = (np.asarray(x, np.int64) for x in sk.export())
+    fire, reset = (np.asarray(x) for x in F.lif_luts(4, 2, P.p))
+    r = np.mod(m, P.p)
+    want_s = np.mod(fire[r] + 1, P.p)
+    want_v = np.mod(reset[r], P.p)
+    err_in = _centred_error(_phase(s, got_h, P.n + 1), r, 2 ** 32 // P.p)
+    sigma_ms = math.sqrt((1 + P.n / 2) / (12 * (2 * P.N) ** 2))
+    near_edge = np.abs(err_in) > 0.5 / P.p - 5 * sigma_ms
+    for got, want in ((got_s, want_s), (got_v, want_v)):
+        bad = F.decrypt(sk, got) != np.where(want > P.p // 2, want - P.p, want)
+        assert np.all(near_edge[bad]), np.nonzero(bad)[0]
+    ok = ~near_edge
+    err = _centred_error(_phase(z, got_s[ok], P.N + 1), want_s[ok], 2 ** 32 // P.p)
+    var_pred = _model_variance(P, keyswitch=False)
+    ratio = err.var(ddof=1) / var_pred
+    print(f"\nkey switch first, output noise: std 2^{math.log2(err.std()):.3f}, "
+          f"model 2^{math.log2(math.sqrt(var_pred)):.3f} (ratio of variances {ratio:.3f}); "
+          f"{int(near_edge.sum())} inputs near an edge")
+    assert 0.7 < ratio < 1.3
+
+
 def test_shape_b_blind_rotation_decrypts_before_key_switch(gpu_env):
     """N = 2048, p = 64: every message x 16 through Fire, checked on the
     extracted sample under z (after the key switch a 4.7 % failure rate is

@@ -149,6 +149,53 @@ def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
     assert np.array_equal(_host(vv), vnew)
 
 
+@pytest.mark.parametrize("shape,count,split", [(0, 1, True), (0, 37, True), (0, 37, False),
+                                               (0, 600, False), (1, 3, True), (1, 5, False)])
+def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, split):
+    """Key switch of LWE_z(H), then Fire and Reset rotations extracted
+    straight into the two outputs under z (one- and two-group kernels,
+    ragged batch sizes): the oracle recomputes sampled neurons; at N = 1024
+    every neuron also decrypts to the LIF functions of its message."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(shape)
+    ok = okeys_a if shape == 0 else okeys_b
+    m = synth.messages(synth.SEED_DATA, count, P.p, stream=800 + count)
+    h = F.encrypt_z(sk, m, synth.SEED_ENC, 60000 + 1000 * shape + count)
+    s2 = torch.zeros((count, P.N + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    prev = ctx.set_split(1 << 20 if split else 0)
+    try:
+        F.pbs_lif_ks_first(ctx, dk, 4, 2, _dev(h), s2, vv)
+    finally:
+        ctx.set_split(prev)
+    got_s, got_v = _host(s2), _host(vv)
+    idx = sorted({0, count // 2, count - 1})
+    spikes, vnew = O.lif_step_ks_first(ok, 4, 2, h[idx])
+    assert np.array_equal(got_s[idx], spikes)
+    assert np.array_equal(got_v[idx], vnew)
+    if shape == 0:
+        # the input error after the key switch is ~4.5 sigma from a window
+        # edge: a rare flip (7e-6 per neuron) is the scheme's, not the kernel's
+        wrong = (F.decrypt(sk, got_s) != O.centred(P.p, O.plain_fire(P.p, 4, m))).sum()
+        wrong += (F.decrypt(sk, got_v) != O.centred(P.p, O.plain_reset(P.p, 4, 2, m))).sum()
+        assert wrong <= 1, wrong
+
+
+def test_pbs_lif_key_switch_first_output_may_alias_input(gpu_env, okeys_a):
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m = synth.messages(synth.SEED_DATA, 9, P.p, stream=899)
+    h = F.encrypt_z(sk, m, synth.SEED_ENC, 61000)
+    hv = _dev(h)
+    s2 = torch.zeros((9, P.N + 1), dtype=torch.int32, device="cuda")
+    F.pbs_lif_ks_first(ctx, dk, 4, 2, hv, s2, hv)  # V' overwrites H
+    spikes, vnew = O.lif_step_ks_first(okeys_a, 4, 2, h[[0, 8]])
+    assert np.array_equal(_host(s2)[[0, 8]], spikes)
+    assert np.array_equal(_host(hv)[[0, 8]], vnew)
+    with pytest.raises(ValueError):
+        F.pbs_lif_ks_first(ctx, dk, 4, 2, hv, s2[:, : P.n + 1].contiguous(), hv)
+
+
 @pytest.mark.parametrize("count", [1, 21, 64, 65, 200])
 def test_keyswitch_bit_exact(gpu_env, okeys_a, count):
     """Ragged batch sizes around the 64-sample groups of the matrix-core

@@ -48,6 +48,17 @@ def test_encrypt_decrypt_match_oracle(okeys_a):
     assert np.array_equal(F.decrypt(sk, ct), m)
 
 
+def test_encrypt_under_z_matches_oracle(okeys_a):
+    P = F.params_default(0)
+    sk, _ = F.keygen(P, synth.SEED_KEYS)
+    m = synth.messages(synth.SEED_DATA, 200, P.p)
+    ct = F.encrypt_z(sk, m, synth.SEED_ENC, 40000)
+    assert ct.shape == (200, P.N + 1)
+    assert np.array_equal(ct, O.encrypt_z(O.SHAPE_A, okeys_a.z, m, synth.SEED_ENC, 40000))
+    assert np.array_equal(F.decrypt(sk, ct), m)
+    assert np.array_equal(O.decrypt(P.p, okeys_a.z, ct), m)
+
+
 @pytest.mark.parametrize("p,V,tau", [(32, 4, 2), (32, 4, 0), (64, 9, 3), (32, 16, 2)])
 def test_program_functions_match_oracle(p, V, tau):
     fire, reset = F.lif_luts(V, tau, p)

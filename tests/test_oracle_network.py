@@ -23,6 +23,32 @@ def test_tiny_lif_layer_encrypted_equals_plaintext(okeys_a):
         assert np.array_equal(O.decrypt(P.p, okeys_a.s, Vs[t]), O.centred(P.p, pV[t])), t
 
 
+def test_tiny_lif_layer_key_switch_first_equals_plaintext(okeys_a):
+    """The same layer with the key switch in front of each blind rotation:
+    inputs and states under z, decrypted with z, spike for spike with the
+    plaintext SNN; the spike outputs' error is that of blind rotation alone."""
+    P = O.SHAPE_A
+    cfg = synth.TinyLIF()
+    x, W = cfg.data()
+    x_ct = O.encrypt_z(P, okeys_a.z, x, synth.SEED_ENC)
+    assert x_ct.shape == (x.size, P.N + 1)
+    I_ct = O.lwe_linear(W, x_ct)
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I_ct, cfg.vth, cfg.tau, cfg.T, ks_first=True)
+    I = (W.astype(np.int64) @ x.astype(np.int64))
+    pH, pS, pV = O.plain_lif_layer_run(P.p, I, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        assert Ss[t].shape == (cfg.neurons, P.N + 1)
+        assert np.array_equal(O.decrypt(P.p, okeys_a.z, Hs[t]), O.centred(P.p, pH[t])), t
+        assert np.array_equal(O.decrypt(P.p, okeys_a.z, Ss[t]), O.centred(P.p, pS[t])), t
+        assert np.array_equal(O.decrypt(P.p, okeys_a.z, Vs[t]), O.centred(P.p, pV[t])), t
+    # spike outputs: blind-rotation noise only (std 2^-8.85 by the standard
+    # analysis), far inside the half window 1/64; with the key switch after
+    # the rotation it would be 2^-8.15
+    err = (O.phase(okeys_a.z, Ss[-1]).astype(np.int64) - (pS[-1] % P.p) * P.delta) & 0xFFFFFFFF
+    err = np.where(err >= 2 ** 31, err - 2 ** 32, err) / 2.0 ** 32
+    assert np.abs(err).max() < 4.5 * 2.0 ** -8.85
+
+
 def test_sum_pool_decrypts_to_window_sums(okeys_a):
     """Average-pool numerator on ciphertexts (Sec. 3.3): the window sums of
     the decrypted grid, computed here by reshaping into k x k blocks."""
