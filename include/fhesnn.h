@@ -136,6 +136,15 @@ FS_API void fs_evk_free(fs_evk* evk);
  * for all r (the condition of Theorem 2.1).  v_out: host [N]. */
 FS_API int fs_test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v_out);
 
+/* Test polynomial that also changes the message space (the dynamic message
+ * space of DiNN that Sec. 5.1 notes applies here): inputs encode Z_p_in
+ * (Delta_in = 2^32/p_in), outputs Z_p_out (Delta_out = 2^32/p_out):
+ * v_i = Delta_out * f(floor((i p_in + N) / (2N)) mod p_in).  f: host [p_in]
+ * values taken mod p_out; FS_EINVAL unless f(r + p_in/2) = -f(r) mod p_out
+ * for all r.  N, p_in, p_out powers of two, p_in <= 2N, p_out <= 2^31. */
+FS_API int fs_test_poly_mspace(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f,
+                               uint32_t* v_out);
+
 /* FHE-Fire and FHE-Reset program functions (Sec. 4.2) as residue tables:
  * fire[r] = +1 if (r - V_th) mod p < p/2 else -1;
  * reset[r] = leak(r) on [0, V_th), 0 on [V_th, p/2), -leak(r - p/2) on
@@ -231,6 +240,15 @@ FS_API int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const ui
  * the Fire function.  h, spike2_out, v_out: dev [B][n+1]; v_out may alias h. */
 FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
                uint32_t* spike2_out, uint32_t* v_out, void* stream);
+
+/* fs_pbs with a change of message space (test polynomial of
+ * fs_test_poly_mspace): inputs carry messages of Z_p_in, outputs
+ * LWE(f(m)) with Delta_out = 2^32/p_out, e.g. a larger p_out so that the
+ * next WeightSum does not wrap, or a smaller one to widen the decryption
+ * margin.  Layout, keyswitch and errors as fs_pbs. */
+FS_API int fs_pbs_mspace(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, uint32_t p_in,
+                         uint32_t p_out, const uint32_t* in, size_t B, uint32_t* out,
+                         int keyswitch, void* stream);
 
 /* The LIF activation in the key-switch-first order (the bootstrapping of
  * Sec. 2.1 with its Key Switching step moved in front of the Blind

@@ -323,6 +323,29 @@ OR_API int or_test_poly(uint32_t N, uint32_t p, const int32_t *f, uint32_t *v) {
   return 0;
 }
 
+/* The same with a different output message space (the message-space change
+ * of the bootstrapping that Sec. 5.1 borrows from DiNN): inputs encode
+ * Z_p_in with Delta_in = 2^32/p_in, f maps Z_p_in to Z_p_out, and
+ * v_i = (2^32/p_out) f(floor((i p_in + N)/(2N)) mod p_in).  The rotation
+ * by a phase in the upper half negates, so f must satisfy
+ * f(r + p_in/2) = -f(r) mod p_out. */
+OR_API int or_test_poly_ms(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t *f,
+                           uint32_t *v) {
+  const int64_t q = p_out;
+  for (uint32_t r = 0; r < p_in; r++) {
+    int64_t a = ((int64_t)f[(r + p_in / 2) % p_in] % q + q) % q;
+    int64_t b = ((-(int64_t)f[r]) % q + q) % q;
+    if (a != b) return -1;
+  }
+  const uint32_t delta = (uint32_t)(0x100000000ull / p_out);
+  for (uint32_t i = 0; i < N; i++) {
+    uint64_t idx = ((uint64_t)i * p_in + N) / (2ull * N);
+    int64_t val = ((int64_t)f[idx % p_in] % q + q) % q;
+    v[i] = (uint32_t)val * delta;
+  }
+  return 0;
+}
+
 /* Switch a torus value to Z_{2N}: round(x * 2N / 2^32), ties up. */
 OR_API uint32_t or_mod_switch(uint32_t x, uint32_t N) {
   uint32_t nu = or_log2(2 * N);

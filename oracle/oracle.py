@@ -78,6 +78,7 @@ def lib():
             "or_decrypt": (None, [u32, i32p, u32, u32p, sz, i32p]),
             "or_phase": (None, [i32p, u32, u32p, sz, u32p]),
             "or_test_poly": (ctypes.c_int, [u32, u32, i32p, u32p]),
+            "or_test_poly_ms": (ctypes.c_int, [u32, u32, u32, i32p, u32p]),
             "or_mod_switch": (u32, [u32, u32]),
             "or_gadget_digits": (None, [u32, u32, u32, i32p]),
             "or_blind_rotate": (None, [P, u32p, u32p, u32p, u32p]),
@@ -258,10 +259,15 @@ def gadget_digits(x: int, l: int, bg_bit: int):
     return d
 
 
-def test_poly(N: int, p: int, f):
+def test_poly(N: int, p: int, f, p_out: int | None = None):
+    """Test polynomial of f: Z_p -> Z_p, or f: Z_p -> Z_p_out when p_out is
+    given (outputs encoded with 2^32 / p_out)."""
     f = _c(f, np.int32)
     v = np.zeros(N, np.uint32)
-    rc = lib().or_test_poly(N, p, _i32(f), _u32(v))
+    if p_out is None:
+        rc = lib().or_test_poly(N, p, _i32(f), _u32(v))
+    else:
+        rc = lib().or_test_poly_ms(N, p, p_out, _i32(f), _u32(v))
     if rc != 0:
         raise ValueError("program function is not negacyclic: f(r+p/2) != -f(r)")
     return v

@@ -183,18 +183,22 @@ int ensure_ext(fs_ctx* ctx, size_t words) {
   return FS_OK;
 }
 
-// device test polynomial of a residue table (cached per context)
-int get_tpoly(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f, uint32_t** out) {
+// device test polynomial of a residue table f: Z_p -> Z_p_out (p_out = 0:
+// the same space), cached per context
+int get_tpoly(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f, uint32_t** out,
+              uint32_t p_out = 0) {
+  if (p_out == 0) p_out = p;
   std::vector<int32_t> key(f, f + p);
   key.push_back((int32_t)N);
   key.push_back((int32_t)p);
+  key.push_back((int32_t)p_out);
   auto it = ctx->tpoly.find(key);
   if (it != ctx->tpoly.end()) {
     *out = it->second;
     return FS_OK;
   }
   std::vector<uint32_t> v(N);
-  int rc = test_poly(N, p, f, v.data());
+  int rc = test_poly_ms(N, p, p_out, f, v.data());
   if (rc) return rc;
   uint32_t* d = nullptr;
   FS_HIP(hipMalloc(&d, N * sizeof(uint32_t)));
@@ -356,6 +360,20 @@ int fs_test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v_out) {
   if (N < 2 || (N & (N - 1)) || p < 2 || (p & (p - 1)) || p > 2 * N)
     return fail(FS_EINVAL, "fs_test_poly: N and p must be powers of two with p <= 2N");
   return test_poly(N, p, f, v_out);
+}
+
+static bool pow2_in(uint64_t x, uint64_t lo, uint64_t hi) {
+  return x >= lo && x <= hi && (x & (x - 1)) == 0;
+}
+
+int fs_test_poly_mspace(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f,
+                        uint32_t* v_out) {
+  if (!f || !v_out) return fail(FS_EINVAL, "fs_test_poly_mspace: null argument");
+  if (!pow2_in(N, 2, 1u << 20) || !pow2_in(p_in, 2, 2ull * N) || !pow2_in(p_out, 2, 1u << 31))
+    return fail(FS_EINVAL,
+                "fs_test_poly_mspace: N, p_in, p_out must be powers of two, p_in <= 2N, "
+                "p_out <= 2^31");
+  return test_poly_ms(N, p_in, p_out, f, v_out);
 }
 
 int fs_lif_luts(const fs_lif* lif, uint32_t p, int32_t* fire, int32_t* reset) {
@@ -555,6 +573,25 @@ int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const uint32_t*
   DeviceGuard g(ctx->device);
   uint32_t* tp[2] = {nullptr, nullptr};
   int rc = get_tpoly(ctx, dk->prm.N, dk->prm.p, lut, &tp[0]);
+  if (rc) return rc;
+  const uint32_t zero[2] = {0u, 0u};
+  return run_pbs(ctx, dk, tp, 1, in, B, out, nullptr, zero, keyswitch, as_stream(stream));
+}
+
+int fs_pbs_mspace(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, uint32_t p_in,
+                  uint32_t p_out, const uint32_t* in, size_t B, uint32_t* out, int keyswitch,
+                  void* stream) {
+  if (!ctx || !dk || !lut || (B && (!in || !out)))
+    return fail(FS_EINVAL, "fs_pbs_mspace: null argument");
+  if (dk->device != ctx->device) return fail(FS_EPARAM, "fs_pbs_mspace: key lives on another device");
+  if (B > 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_mspace: batch too large");
+  if (!pow2_in(p_in, 2, 2ull * dk->prm.N) || !pow2_in(p_out, 2, 1u << 31))
+    return fail(FS_EINVAL, "fs_pbs_mspace: p_in, p_out must be powers of two, p_in <= 2N, "
+                           "p_out <= 2^31");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  int rc = get_tpoly(ctx, dk->prm.N, p_in, lut, &tp[0], p_out);
   if (rc) return rc;
   const uint32_t zero[2] = {0u, 0u};
   return run_pbs(ctx, dk, tp, 1, in, B, out, nullptr, zero, keyswitch, as_stream(stream));

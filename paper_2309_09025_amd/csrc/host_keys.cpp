@@ -214,16 +214,23 @@ int decrypt(const Secret& sk, const uint32_t* ct, size_t count, uint32_t dim, in
 // ------------------------------------------------------------------ program functions
 
 int test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v) {
-  const uint32_t mask = p - 1;
-  for (uint32_t r = 0; r < p; ++r)
-    if ((((uint32_t)f[(r + p / 2) & mask] + (uint32_t)f[r]) & mask) != 0)
+  return test_poly_ms(N, p, p, f, v);
+}
+
+// Input messages in Z_p_in (phase window of coefficient i: message
+// floor((i p_in + N) / 2N), i.e. i p_in / 2N rounded half up), outputs in
+// Z_p_out with Delta_out = 2^32 / p_out.  A phase in the upper half of the
+// torus rotates the polynomial past X^N = -1, hence the negacyclic
+// condition f(r + p_in/2) = -f(r) mod p_out.
+int test_poly_ms(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f, uint32_t* v) {
+  const uint32_t in_mask = p_in - 1, out_mask = p_out - 1;
+  for (uint32_t r = 0; r < p_in; ++r)
+    if ((((uint32_t)f[(r + p_in / 2) & in_mask] + (uint32_t)f[r]) & out_mask) != 0)
       return fail(FS_EINVAL, "program function violates f(r + p/2) = -f(r) (Theorem 2.1)");
-  const uint32_t delta = delta_of(p);
-  // window of coefficient i: message floor((i p + N) / 2N), i.e. i p / 2N
-  // rounded half up
+  const uint32_t delta = delta_of(p_out);
   for (uint32_t i = 0; i < N; ++i) {
-    const uint32_t msg = (uint32_t)(((uint64_t)i * p + N) / (2ull * N)) & mask;
-    v[i] = ((uint32_t)f[msg] & mask) * delta;
+    const uint32_t msg = (uint32_t)(((uint64_t)i * p_in + N) / (2ull * N)) & in_mask;
+    v[i] = ((uint32_t)f[msg] & out_mask) * delta;
   }
   return FS_OK;
 }

@@ -74,6 +74,7 @@ SIGNATURES = {
     "fs_secret_free": (None, [_vp]),
     "fs_evk_free": (None, [_vp]),
     "fs_test_poly": (_int, [_u32, _u32, _i32p, _u32p]),
+    "fs_test_poly_mspace": (_int, [_u32, _u32, _u32, _i32p, _u32p]),
     "fs_lif_luts": (_int, [_LP, _u32, _i32p, _i32p]),
     "fs_lif_range_check": (_int, [_LP, _u32, _i32p, _sz, _sz, _i32, _i32, _i64p]),
     "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
@@ -92,6 +93,7 @@ SIGNATURES = {
     "fs_lwe_add_plain": (_int, [_vp, _u32, _vp, _vp, _sz, _u32, _vp, _vp]),
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
+    "fs_pbs_mspace": (_int, [_vp, _vp, _i32p, _u32, _u32, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif_ks_first": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
@@ -237,6 +239,16 @@ def test_poly(N: int, p: int, f) -> np.ndarray:
     return v
 
 
+def test_poly_mspace(N: int, p_in: int, p_out: int, f) -> np.ndarray:
+    f, fp = _np_i32(f)
+    if f.size != p_in:
+        raise ValueError(f"test_poly_mspace: f must have p_in = {p_in} entries")
+    v = np.zeros(N, np.uint32)
+    _check("fs_test_poly_mspace",
+           lib().fs_test_poly_mspace(N, p_in, p_out, fp, v.ctypes.data_as(_u32p)))
+    return v
+
+
 def lif_luts(v_th: int, tau: int, p: int):
     fire = np.zeros(p, np.int32)
     reset = np.zeros(p, np.int32)
@@ -342,10 +354,35 @@ def lwe_add_plain(ctx: Context, p: int, x, c, y, stream=None):
     return y
 
 
+def _pbs_shapes(fn, dk, x, out, keyswitch):
+    P = dk.params
+    wo = P.n + 1 if keyswitch else P.N + 1
+    if x.dim() != 2 or x.shape[1] != P.n + 1:
+        raise ValueError(f"{fn}: inputs must be [B][{P.n + 1}]")
+    if out.dim() != 2 or out.shape[0] != x.shape[0] or out.shape[1] != wo:
+        raise ValueError(f"{fn}: outputs must be [{x.shape[0]}][{wo}]")
+
+
 def pbs(ctx: Context, dk: DevKey, lut, x, out, keyswitch: bool = True, stream=None):
     lut, lp = _np_i32(lut)
+    if lut.size != dk.params.p:
+        raise ValueError(f"pbs: the program function needs p = {dk.params.p} entries")
+    _pbs_shapes("pbs", dk, x, out, keyswitch)
     _check("fs_pbs", lib().fs_pbs(ctx.h, dk.h, lp, _dptr(x), x.shape[0], _dptr(out),
                                   1 if keyswitch else 0, _stream(stream)))
+    return out
+
+
+def pbs_mspace(ctx: Context, dk: DevKey, lut, p_in: int, p_out: int, x, out,
+               keyswitch: bool = True, stream=None):
+    """Bootstrapping f: Z_p_in -> Z_p_out (outputs encoded with 2^32 / p_out)."""
+    lut, lp = _np_i32(lut)
+    if lut.size != p_in:
+        raise ValueError(f"pbs_mspace: the program function needs p_in = {p_in} entries")
+    _pbs_shapes("pbs_mspace", dk, x, out, keyswitch)
+    _check("fs_pbs_mspace", lib().fs_pbs_mspace(ctx.h, dk.h, lp, p_in, p_out, _dptr(x),
+                                                x.shape[0], _dptr(out), 1 if keyswitch else 0,
+                                                _stream(stream)))
     return out
 
 

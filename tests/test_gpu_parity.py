@@ -123,6 +123,35 @@ def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count,
         ctx.set_split(prev)
 
 
+@pytest.mark.parametrize("p_in,p_out,keyswitch", [(16, 32, True), (32, 8, True), (32, 8, False),
+                                                   (64, 2 ** 20, False)])
+def test_pbs_message_space_change_bit_exact(gpu_env, okeys_a, p_in, p_out, keyswitch):
+    """f: Z_p_in -> Z_p_out (k -> 3k + 1 on the lower half, extended
+    negacyclically): bits equal to the oracle's; where the output space keeps
+    a wide decryption margin (p_out = 8) every output decrypts to f."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    h = p_in // 2
+    f = np.array([3 * k + 1 if k < h else -(3 * (k - h) + 1) for k in range(p_in)], np.int32)
+    k = synth.rng(synth.SEED_DATA, 850 + p_in).integers(0, p_in, size=40).astype(np.int32)
+    if p_in <= P.p:  # message k of Z_p_in is message k p / p_in of the key's Z_p
+        ct = F.encrypt(sk, k * (P.p // p_in), synth.SEED_ENC, 62000 + p_in)
+    else:  # a finer space than the key's: an encryption of 0 plus k 2^32 / p_in
+        ct = F.encrypt(sk, np.zeros_like(k), synth.SEED_ENC, 62000 + p_in)
+        ct[:, -1] += (k.astype(np.int64) * (2 ** 32 // p_in)).astype(np.uint32)
+    width = P.n + 1 if keyswitch else P.N + 1
+    out = torch.zeros((k.size, width), dtype=torch.int32, device="cuda")
+    F.pbs_mspace(ctx, dk, f, p_in, p_out, _dev(ct), out, keyswitch=keyswitch)
+    got = _host(out)
+    want = O.pbs(okeys_a, O.test_poly(P.N, p_in, f, p_out), ct, keyswitch=keyswitch)
+    assert np.array_equal(got, want)
+    if p_out == 8:
+        key = okeys_a.s if keyswitch else okeys_a.z
+        assert np.array_equal(O.decrypt(p_out, key, got), O.centred(p_out, f[k] % p_out))
+    with pytest.raises(ValueError):
+        F.pbs_mspace(ctx, dk, f[:-1], p_in, p_out, _dev(ct), out, keyswitch=keyswitch)
+
+
 def test_pbs_lif_bit_exact(gpu_env, okeys_a):
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)

@@ -69,6 +69,16 @@ def test_program_functions_match_oracle(p, V, tau):
         assert np.array_equal(F.test_poly(N, p, reset), O.test_poly(N, p, reset))
 
 
+@pytest.mark.parametrize("N,p_in,p_out", [(1024, 16, 64), (1024, 32, 8), (2048, 64, 2 ** 20),
+                                          (1024, 2048, 4)])
+def test_message_space_test_poly_matches_oracle(N, p_in, p_out):
+    h = p_in // 2
+    f = np.array([(5 * k + 1) if k < h else -(5 * (k - h) + 1) for k in range(p_in)], np.int32)
+    assert np.array_equal(F.test_poly_mspace(N, p_in, p_out, f), O.test_poly(N, p_in, f, p_out))
+    with pytest.raises(F.FsError):
+        F.test_poly_mspace(N, 4 * N, p_out, np.zeros(4 * N, np.int32))  # p_in > 2N
+
+
 def test_errors_are_reported_not_raised_in_c():
     bad = O.lut_reset(32, 4, 2).copy()
     bad[17] = 15  # the printed fourth branch p/2 - leak: not negacyclic

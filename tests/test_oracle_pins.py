@@ -182,6 +182,20 @@ def test_test_poly_windows():
         assert int(v[i]) == (int(f[m]) % p) * delta
 
 
+def test_test_poly_message_space_change_hand_example():
+    """N = 8, p_in = 4, p_out = 32, f = (1, 2, -1, -2): coefficient i carries
+    f(round(i p_in / 2N)) = f(floor((4 i + 8) / 16)) -> messages
+    (0, 0, 1, 1, 1, 1, 2, 2), values (1, 1, 2, 2, 2, 2, -1, -1), times
+    Delta_out = 2^27."""
+    v = O.test_poly(8, 4, [1, 2, -1, -2], p_out=32)
+    assert [int(x) for x in v] == [x * 2 ** 27 for x in (1, 1, 2, 2, 2, 2, 31, 31)]
+    with pytest.raises(ValueError):  # f(r + 2) = -f(r) mod 32 fails for r = 0
+        O.test_poly(8, 4, [1, 2, 1, -2], p_out=32)
+    # the same space reduces to the plain definition
+    f = O.lut_fire(32, 4)
+    assert np.array_equal(O.test_poly(1024, 32, f, p_out=32), O.test_poly(1024, 32, f))
+
+
 # ------------------------------------------------------------------ P8: encryption
 
 def test_encrypt_decrypt_all_messages(okeys_a):
@@ -265,6 +279,26 @@ def test_pbs_computes_the_program_function(okeys_a):
     reset = O.decrypt(P.p, okeys_a.s, O.pbs(okeys_a, vr, ct))
     assert list(fire) == list(O.centred(P.p, O.lut_fire(P.p, 4)[m % P.p]))
     assert list(reset) == list(O.centred(P.p, O.lut_reset(P.p, 4, 2)[m % P.p]))
+
+
+def _triple_map(p_in, p_out):
+    """f(k) = 3k on [0, p_in/2), extended negacyclically: f(k + p_in/2) = -f(k)."""
+    h = p_in // 2
+    return np.array([3 * k if k < h else -3 * (k - h) for k in range(p_in)], np.int32) % p_out
+
+
+def test_pbs_changes_the_message_space(okeys_a):
+    """Inputs in Z_16 (even messages of Z_32: Delta_16 = 2 Delta_32), f(k) = 3k
+    (negacyclic extension), outputs decrypted in Z_32: every message maps to
+    f(k) mod 32.  (Z_64 outputs would decrypt with a 2.2-sigma margin at
+    these parameters: the output space must keep 1/(2 p_out) above the
+    bootstrapping's output noise.)"""
+    P = O.SHAPE_A
+    k = np.arange(16, dtype=np.int32)
+    ct = O.encrypt(P, okeys_a.s, 2 * k, 11)
+    f = _triple_map(16, 32)
+    out = O.pbs(okeys_a, O.test_poly(P.N, 16, f, p_out=32), ct)
+    assert list(O.decrypt(32, okeys_a.s, out)) == list(O.centred(32, f[k]))
 
 
 # ------------------------------------------------------------------ WeightSum
