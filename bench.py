@@ -172,30 +172,50 @@ def _conv_nets(synth, widths):
     return Wc, nets
 
 
-def single_image(F, NW, synth, ctx, dk, sk, images=3):
-    """Conv SNN on one 28x28 image at a time (T = 4, hidden 256), each
-    timestep replayed from a HIP graph; encrypted image resident in HBM."""
+def _image_latency(run, args_of, images):
+    """Mean wall time of run(*args_of(k)) over images k = 0..images-1, after
+    one warm-up on image `images` (caches, graphs, scratch)."""
     import torch
+    run(*args_of(images))
+    torch.cuda.synchronize()
+    lat = []
+    for k in range(images):
+        a = args_of(k)
+        t0 = time.perf_counter()
+        run(*a)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    return sum(lat) / len(lat)
+
+
+def _single_image_record(workload, pbs, m_steps, m_pipe):
+    """Prediction rate of the faster schedule, with both latencies."""
+    m = min(m_steps, m_pipe)
+    return {"workload": workload,
+            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
+            "schedule": "pipelined" if m_pipe <= m_steps else "per-step graphs",
+            "per_step_graphs_ms": round(m_steps * 1e3, 2),
+            "pipelined_ms": round(m_pipe * 1e3, 2),
+            "bootstrappings_per_image": pbs, "pbs_per_s": round(pbs / m, 1)}
+
+
+def single_image(F, NW, synth, ctx, dk, sk, images=3):
+    """Conv SNN on one 28x28 image at a time (T = 4, hidden 256), encrypted
+    image resident in HBM, in two schedules: each timestep replayed from a
+    HIP graph, and the layers software-pipelined over time (layer 1 at step
+    t+1 in the same launch as layer 2 at step t)."""
     cfg = synth.CONV_SNN
     px, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=True)
     cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
            for k in range(images + 1)]
-    net.run(cts[-1], cfg.T)  # warm (caches, graph)
-    torch.cuda.synchronize()
-    lat = []
-    for k in range(images):
-        t0 = time.perf_counter()
-        net.run(cts[k], cfg.T)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-    m = sum(lat) / len(lat)
-    return {"workload": "conv SNN, 1 synthetic 28x28 image, conv 1->8 5x5 s2 p2 (LIF) -> FC 1568->256 "
-                        "(LIF) -> FC 256->10 accumulators, T=4",
-            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
-            "bootstrappings_per_image": cfg.pbs_count(),
-            "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+    args_of = lambda k: (cts[k], cfg.T)
+    m_steps = _image_latency(net.run, args_of, images)
+    m_pipe = _image_latency(net.run_pipelined, args_of, images)
+    return _single_image_record(
+        "conv SNN, 1 synthetic 28x28 image, conv 1->8 5x5 s2 p2 (LIF) -> FC 1568->256 "
+        "(LIF) -> FC 256->10 accumulators, T=4", cfg.pbs_count(), m_steps, m_pipe)
 
 
 def tiny_lif(F, NW, synth, ctx, dk, sk, reps=5):
@@ -250,56 +270,39 @@ def lif_orders(F, synth, ctx, dk, sk, neurons=2048, reps=3):
 def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
     """The paper's CSNN topology on one image at a time (conv 10x8x8 s2 p1
     (LIF) -> 2x2 pool folded into FC 360->160 (LIF) -> FC 160->10 (LIF),
-    spike-count scores, T = 4), each timestep replayed from a HIP graph."""
-    import torch
+    spike-count scores, T = 4), per-step graphs and pipelined."""
     cfg = synth.PAPER_CSNN
     _, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau))
     cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
            for k in range(images + 1)]
-    net.run(cts[-1], cfg.T)  # warm (caches, graph)
-    torch.cuda.synchronize()
-    lat = []
-    for k in range(images):
-        t0 = time.perf_counter()
-        net.run(cts[k], cfg.T)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-    m = sum(lat) / len(lat)
-    return {"workload": "paper CSNN topology, 1 synthetic 28x28 image, conv 1->10 8x8 s2 p1 (LIF) "
-                        "-> 2x2 average pool folded into FC 360->160 (LIF) -> FC 160->10 (LIF), "
-                        "spike-count scores, T=4",
-            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
-            "bootstrappings_per_image": cfg.pbs_count(),
-            "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+    args_of = lambda k: (cts[k], cfg.T)
+    m_steps = _image_latency(net.run, args_of, images)
+    m_pipe = _image_latency(net.run_pipelined, args_of, images)
+    return _single_image_record(
+        "paper CSNN topology, 1 synthetic 28x28 image, conv 1->10 8x8 s2 p1 (LIF) "
+        "-> 2x2 average pool folded into FC 360->160 (LIF) -> FC 160->10 (LIF), "
+        "spike-count scores, T=4", cfg.pbs_count(), m_steps, m_pipe)
 
 
 def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
     """The paper's Poisson-encoded SNN on one image at a time (784 Sign
-    bootstrappings per step, FC 784->160 (LIF), FC 160->10 (LIF), T1 = 20)."""
-    import torch
+    bootstrappings per step, FC 784->160 (LIF), FC 160->10 (LIF), T1 = 20),
+    per-step graphs and pipelined."""
     cfg = synth.POISSON_SNN
     _, W1, W2 = cfg.data()
     net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
     cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 5000 * k))
            for k in range(images + 1)]
-    net.run(cts[-1], cfg.thresholds(image_stream=images))  # warm (caches, graph)
-    torch.cuda.synchronize()
-    lat = []
-    for k in range(images):
-        thr = cfg.thresholds(image_stream=k)
-        t0 = time.perf_counter()
-        net.run(cts[k], thr)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-    m = sum(lat) / len(lat)
-    return {"workload": "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
-                        "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "
-                        "spike-count scores, T1=20",
-            "predictions_per_s": round(1.0 / m, 3), "latency_ms": round(m * 1e3, 2),
-            "bootstrappings_per_image": cfg.pbs_count(),
-            "pbs_per_s": round(cfg.pbs_count() / m, 1)}
+    thr = [cfg.thresholds(image_stream=k) for k in range(images + 1)]
+    args_of = lambda k: (cts[k], thr[k])
+    m_steps = _image_latency(net.run, args_of, images)
+    m_pipe = _image_latency(net.run_pipelined, args_of, images)
+    return _single_image_record(
+        "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
+        "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "
+        "spike-count scores, T1=20", cfg.pbs_count(), m_steps, m_pipe)
 
 
 def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):

@@ -160,6 +160,40 @@ class ConvSNN:
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 
+    def run_pipelined(self, px_ct: torch.Tensor, T: int, record: bool = False):
+        """run() with the two LIF layers software-pipelined over time: layer 1
+        at step t+1 depends only on its own state and the static current, so
+        it is bootstrapped in the same launch (fs_pbs_lif_ranges) as layer 2
+        at step t.  T + 1 launches instead of 2T, fewer partly filled rounds
+        for one image; the results are bit-identical to run()."""
+        c, dk, L = self.ctx, self.dk, self.lif
+        F.lwe_conv2d(c, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd, self.stride,
+                     self.pad)
+        for b in (self.V1, self.V2, self.score):
+            b.zero_()
+        steps = [{} for _ in range(T)] if record else []
+        for k in range(T + 1):
+            jobs = []
+            if k >= 1:  # layer 2 at step k-1 reads S1 before this launch overwrites it
+                F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
+                jobs.append((dk, self.H2, self.S2, self.V2))
+            if k < T:
+                F.lwe_add(c, self.V1, self.I1, self.H1)
+                jobs.append((dk, self.H1, self.S1, self.V1))
+            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+            self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
+            if k >= 1:
+                F.lwe_linear(c, self.W2, self.S2, self.score, add=self.score)
+            if record:
+                torch.cuda.synchronize()
+                if k < T:
+                    steps[k].update({n: F.to_host(getattr(self, n)) for n in ("H1", "S1", "V1")})
+                if k >= 1:
+                    steps[k - 1].update({n: F.to_host(getattr(self, n))
+                                         for n in ("H2", "S2", "V2", "score")})
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
 
 def fold_avg_pool(W1: np.ndarray, C: int, H: int, W: int, k: int) -> np.ndarray:
     """Weights of an FC layer over a k x k sum pool, moved onto the unpooled
@@ -236,6 +270,46 @@ class PaperCSNN:
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 
+    def run_pipelined(self, px_ct, T: int, record: bool = False):
+        """run() with the three LIF layers software-pipelined over time: wave
+        k bootstraps layer 1 at step k, layer 2 at step k-1 and layer 3 at
+        step k-2 in one launch (each layer's next step depends on its own
+        state and the previous layer's spikes of the same step).  T + 2
+        launches instead of 3T; bit-identical to run()."""
+        c, dk, L = self.ctx, self.dk, self.lif
+        F.lwe_conv2d(c, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd, self.stride,
+                     self.pad)
+        for b in (self.V1, self.V2, self.V3, self.score):
+            b.zero_()
+        steps = [{} for _ in range(T)] if record else []
+        for k in range(T + 2):
+            jobs = []
+            # inputs first, deepest layer first: each reads the previous
+            # layer's spikes before this wave's launch overwrites them
+            if 2 <= k:
+                F.lwe_linear(c, self.W2, self.S2, self.H3, add=self.V3)
+                jobs.append((dk, self.H3, self.S3, self.V3))
+            if 1 <= k <= T:
+                F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
+                jobs.append((dk, self.H2, self.S2, self.V2))
+            if k < T:
+                F.lwe_add(c, self.V1, self.I1, self.H1)
+                jobs.append((dk, self.H1, self.S1, self.V1))
+            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+            self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
+            if 2 <= k:
+                F.lwe_add(c, self.score, self.S3, self.score)
+            if record:
+                torch.cuda.synchronize()
+                for layer, t in ((1, k), (2, k - 1), (3, k - 2)):
+                    if 0 <= t < T:
+                        steps[t].update({f"{n}{layer}": F.to_host(getattr(self, f"{n}{layer}"))
+                                         for n in ("H", "S", "V")})
+                if 2 <= k:
+                    steps[k - 2]["score"] = F.to_host(self.score)
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
 
 class PoissonSNN:
     """The paper's Poisson-encoded SNN on one encrypted 4-bit image (Sec. 2.3,
@@ -300,6 +374,49 @@ class PoissonSNN:
                 torch.cuda.synchronize()
                 steps.append({k: F.to_host(getattr(self, k)) for k in
                               ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score")})
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
+    def run_pipelined(self, px_ct, thresholds, record: bool = False):
+        """run() software-pipelined over time: wave k codes step k's pixel
+        spikes (one Sign launch) and bootstraps layer 1 at step k-1 and layer
+        2 at step k-2 together (one fs_pbs_lif_ranges launch).  2 launches
+        per step instead of 3; bit-identical to run()."""
+        c, dk, L = self.ctx, self.dk, self.lif
+        T = len(thresholds)
+        self.px.copy_(px_ct)
+        neg = torch.from_numpy(-np.ascontiguousarray(thresholds, np.int32)).to("cuda")
+        for b in (self.V1, self.V2, self.score):
+            b.zero_()
+        steps = [{} for _ in range(T)] if record else []
+        for k in range(T + 2):
+            jobs = []
+            if 2 <= k:  # layer 2 at step k-2 (reads S1 before it is overwritten)
+                F.lwe_linear(c, self.W2, self.S1, self.H2, add=self.V2)
+                jobs.append((dk, self.H2, self.S2, self.V2))
+            if 1 <= k <= T:  # layer 1 at step k-1 (reads S0 before the coding below)
+                F.lwe_linear(c, self.W1, self.S0, self.H1, add=self.V1)
+                jobs.append((dk, self.H1, self.S1, self.V1))
+            if k < T:
+                F.lwe_add_plain(c, self.p, self.px, neg[k], self.H0)
+                F.pbs(c, dk, self.fire1, self.H0, self.S0, keyswitch=True)
+                F.lwe_add_plain(c, self.p, self.S0, self.ones, self.S0)
+                self.pbs_count += self.pixels
+            if jobs:
+                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+                self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
+            if 2 <= k:
+                F.lwe_add(c, self.score, self.S2, self.score)
+            if record:
+                torch.cuda.synchronize()
+                if k < T:
+                    steps[k]["S0"] = F.to_host(self.S0)
+                for layer, t in ((1, k - 1), (2, k - 2)):
+                    if 0 <= t < T:
+                        steps[t].update({f"{n}{layer}": F.to_host(getattr(self, f"{n}{layer}"))
+                                         for n in ("H", "S", "V")})
+                if 2 <= k:
+                    steps[k - 2]["score"] = F.to_host(self.score)
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 

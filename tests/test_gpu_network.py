@@ -56,16 +56,20 @@ def test_tiny_lif_layer_key_switch_first_bit_exact(gpu_env, okeys_a, capture):
         assert np.array_equal(F.decrypt(sk, V), O.centred(P.p, pV[t])), t
 
 
-@pytest.mark.parametrize("capture", [False, True])
-def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, capture):
-    """The conv -> FC -> FC topology at a size the oracle runs end to end."""
+@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined"])
+def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, mode):
+    """The conv -> FC -> FC topology at a size the oracle runs end to end:
+    eager, graph-replayed, and software-pipelined over time (layer 1 at step
+    t+1 bootstrapped in the same launch as layer 2 at step t)."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
     cfg = synth.CONV_SNN_MINI
     px, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
-    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=capture)
-    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau),
+                     capture=mode == "graph")
+    run = net.run_pipelined if mode == "pipelined" else net.run
+    score, steps = run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
     assert net.pbs_count == cfg.pbs_count()
     _, osteps = O.conv_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
                                Wc, W1, W2, geom, cfg.vth, cfg.tau, cfg.T)
@@ -87,8 +91,10 @@ def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
     px, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=True)
-    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
+    score, steps = net.run(x, cfg.T, record=True)
     assert net.pbs_count == cfg.pbs_count() == 14592
+    assert np.array_equal(net.run_pipelined(x, cfg.T)[0], score)  # the pipelined schedule
     octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
     I1 = O.lwe_conv2d(Wc, octs, cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     sample = [0, 1, 97, 784, 1567]
@@ -138,8 +144,8 @@ def test_uneven_batch_equals_images_alone(gpu_env):
         assert np.array_equal(got[k], score), k
 
 
-@pytest.mark.parametrize("capture", [False, True])
-def test_paper_csnn_mini_bit_exact_over_two_images(gpu_env, okeys_a, capture):
+@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined"])
+def test_paper_csnn_mini_bit_exact_over_two_images(gpu_env, okeys_a, mode):
     """The paper's topology (conv -> pool folded into FC1 -> FC -> FC, all
     LIF, spike-count scores) at a size the oracle runs end to end; the same
     network object evaluates two images (the step graph is reused)."""
@@ -149,11 +155,12 @@ def test_paper_csnn_mini_bit_exact_over_two_images(gpu_env, okeys_a, capture):
     _, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau),
-                       capture=capture)
+                       capture=mode == "graph")
+    run = net.run_pipelined if mode == "pipelined" else net.run
     for img in range(2):
         px = cfg.data(image_stream=img)[0]
-        score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC, 4000 * img)), cfg.T,
-                               record=True)
+        score, steps = run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC, 4000 * img)), cfg.T,
+                           record=True)
         _, osteps = O.paper_csnn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC,
                                                         4000 * img),
                                      Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T)
@@ -178,8 +185,10 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
     px, Wc, W1, W2 = cfg.data()
     geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau))
-    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T, record=True)
+    x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
+    score, steps = net.run(x, cfg.T, record=True)
     assert net.pbs_count == cfg.pbs_count() == 3220 * cfg.T
+    assert np.array_equal(net.run_pipelined(x, cfg.T)[0], score)  # the pipelined schedule
     octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
     I1 = O.lwe_conv2d(Wc, octs, cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
     sample = [0, 13, 143, 144, 1000, 1439]
@@ -201,8 +210,8 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
     assert np.array_equal(score, total.astype(np.uint32))
 
 
-@pytest.mark.parametrize("capture", [False, True])
-def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, capture):
+@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined"])
+def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     """The Poisson-encoded SNN (per step: per-pixel plaintext threshold, one
     Sign bootstrapping per pixel, FC (LIF), FC (LIF), spike counts) at a size
     the oracle runs end to end, eager and replayed from a HIP graph."""
@@ -211,8 +220,9 @@ def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, capture):
     cfg = synth.POISSON_SNN_MINI
     px, W1, W2 = cfg.data()
     thr = cfg.thresholds()
-    net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), capture=capture)
-    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
+    net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), capture=mode == "graph")
+    run = net.run_pipelined if mode == "pipelined" else net.run
+    score, steps = run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
     assert net.pbs_count == cfg.pbs_count()
     osteps = O.poisson_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
                                thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
@@ -234,8 +244,10 @@ def test_poisson_snn_full_size_sampled(gpu_env, okeys_a):
     px, W1, W2 = cfg.data()
     thr = cfg.thresholds()
     net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
-    score, steps = net.run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
+    x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
+    score, steps = net.run(x, thr, record=True)
     assert net.pbs_count == cfg.pbs_count() == (784 + 2 * 160 + 2 * 10) * cfg.T
+    assert np.array_equal(net.run_pipelined(x, thr)[0], score)  # the pipelined schedule
     octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
     sample = [0, 300, 404, 783]
     plain = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
