@@ -289,7 +289,7 @@ def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
 def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
     """The paper's Poisson-encoded SNN on one image at a time (784 Sign
     bootstrappings per step, FC 784->160 (LIF), FC 160->10 (LIF), T1 = 20),
-    per-step graphs and pipelined."""
+    per-step graphs and pipelined with the pixel coding on a second stream."""
     cfg = synth.POISSON_SNN
     _, W1, W2 = cfg.data()
     net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
@@ -298,7 +298,8 @@ def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
     thr = [cfg.thresholds(image_stream=k) for k in range(images + 1)]
     args_of = lambda k: (cts[k], thr[k])
     m_steps = _image_latency(net.run, args_of, images)
-    m_pipe = _image_latency(net.run_pipelined, args_of, images)
+    side = F.Context(0)  # the pixel coding on a second stream, beside the LIF launch
+    m_pipe = _image_latency(lambda x, t: net.run_pipelined(x, t, side_ctx=side), args_of, images)
     return _single_image_record(
         "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
         "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "

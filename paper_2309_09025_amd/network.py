@@ -377,17 +377,23 @@ class PoissonSNN:
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 
-    def run_pipelined(self, px_ct, thresholds, record: bool = False):
+    def run_pipelined(self, px_ct, thresholds, record: bool = False, side_ctx=None):
         """run() software-pipelined over time: wave k codes step k's pixel
         spikes (one Sign launch) and bootstraps layer 1 at step k-1 and layer
         2 at step k-2 together (one fs_pbs_lif_ranges launch).  2 launches
-        per step instead of 3; bit-identical to run()."""
+        per step instead of 3; bit-identical to run().  side_ctx: a second
+        Context (its own scratch); the pixel coding then runs on a second
+        stream, concurrently with the same wave's LIF launch, ordered by
+        events against the reads and writes of S0."""
         c, dk, L = self.ctx, self.dk, self.lif
         T = len(thresholds)
         self.px.copy_(px_ct)
         neg = torch.from_numpy(-np.ascontiguousarray(thresholds, np.int32)).to("cuda")
         for b in (self.V1, self.V2, self.score):
             b.zero_()
+        main = torch.cuda.current_stream()
+        side = torch.cuda.Stream() if side_ctx is not None else main
+        cs = side_ctx if side_ctx is not None else c
         steps = [{} for _ in range(T)] if record else []
         for k in range(T + 2):
             jobs = []
@@ -397,16 +403,26 @@ class PoissonSNN:
             if 1 <= k <= T:  # layer 1 at step k-1 (reads S0 before the coding below)
                 F.lwe_linear(c, self.W1, self.S0, self.H1, add=self.V1)
                 jobs.append((dk, self.H1, self.S1, self.V1))
+            coded = None
             if k < T:
-                F.lwe_add_plain(c, self.p, self.px, neg[k], self.H0)
-                F.pbs(c, dk, self.fire1, self.H0, self.S0, keyswitch=True)
-                F.lwe_add_plain(c, self.p, self.S0, self.ones, self.S0)
+                if side is not main:
+                    read = torch.cuda.Event()
+                    read.record(main)  # S0 of step k-1 consumed; thresholds uploaded
+                    side.wait_event(read)
+                F.lwe_add_plain(cs, self.p, self.px, neg[k], self.H0, stream=side)
+                F.pbs(cs, dk, self.fire1, self.H0, self.S0, keyswitch=True, stream=side)
+                F.lwe_add_plain(cs, self.p, self.S0, self.ones, self.S0, stream=side)
                 self.pbs_count += self.pixels
+                if side is not main:
+                    coded = torch.cuda.Event()
+                    coded.record(side)
             if jobs:
-                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, stream=main)
                 self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
             if 2 <= k:
                 F.lwe_add(c, self.score, self.S2, self.score)
+            if coded is not None:
+                main.wait_event(coded)  # the next wave reads S0 of step k
             if record:
                 torch.cuda.synchronize()
                 if k < T:

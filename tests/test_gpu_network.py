@@ -210,7 +210,7 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
     assert np.array_equal(score, total.astype(np.uint32))
 
 
-@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined"])
+@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined", "two-streams"])
 def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     """The Poisson-encoded SNN (per step: per-pixel plaintext threshold, one
     Sign bootstrapping per pixel, FC (LIF), FC (LIF), spike counts) at a size
@@ -221,8 +221,12 @@ def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     px, W1, W2 = cfg.data()
     thr = cfg.thresholds()
     net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), capture=mode == "graph")
-    run = net.run_pipelined if mode == "pipelined" else net.run
-    score, steps = run(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), thr, record=True)
+    x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
+    if mode == "two-streams":  # pixel coding on a second stream and context
+        score, steps = net.run_pipelined(x, thr, record=True, side_ctx=F.Context(0))
+    else:
+        run = net.run_pipelined if mode == "pipelined" else net.run
+        score, steps = run(x, thr, record=True)
     assert net.pbs_count == cfg.pbs_count()
     osteps = O.poisson_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
                                thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
@@ -247,7 +251,8 @@ def test_poisson_snn_full_size_sampled(gpu_env, okeys_a):
     x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
     score, steps = net.run(x, thr, record=True)
     assert net.pbs_count == cfg.pbs_count() == (784 + 2 * 160 + 2 * 10) * cfg.T
-    assert np.array_equal(net.run_pipelined(x, thr)[0], score)  # the pipelined schedule
+    assert np.array_equal(net.run_pipelined(x, thr)[0], score)  # the pipelined schedules
+    assert np.array_equal(net.run_pipelined(x, thr, side_ctx=F.Context(0))[0], score)
     octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
     sample = [0, 300, 404, 783]
     plain = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
