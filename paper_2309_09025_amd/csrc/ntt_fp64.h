@@ -57,6 +57,15 @@ __device__ __forceinline__ T ldg(const T* base, uint32_t i) {
   return *(gptr<T>)((gchar)as_global(base) + i * (uint32_t)sizeof(T));
 }
 
+// A pointer that is the same in every lane, moved into scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 // A read-only table of doubles addressed through a raw buffer descriptor:
 // the descriptor lives in scalar registers and a load takes a per-lane
 // 32-bit byte offset plus a uniform one, so a group of loads whose offsets

@@ -93,7 +93,10 @@ blind_rotate_kernel(BrArgs a) {
   double* lds = lds_all[grp];
   const size_t job = blockIdx.x;
   const uint32_t n = a.n;
-  const uint64_t g = job / a.nlut;  // ciphertext of this job
+  // ciphertext and program function of this job (nlut is 1 or 2: shifts,
+  // which stay on the scalar unit, unlike a 64-bit division)
+  const uint64_t g = a.nlut == 2 ? job >> 1 : job;
+  const uint32_t lut = a.nlut == 2 ? (uint32_t)(job & 1u) : 0u;
   const uint32_t* ct;
   const double* bsk;
   if (a.ranges) {  // multi-key launch: the range of g gives input and key
@@ -104,8 +107,13 @@ blind_rotate_kernel(BrArgs a) {
     ct = a.in + g * (size_t)(n + 1);
     bsk = a.bsk;
   }
+  // both depend on the workgroup only: pin them to scalar registers, so the
+  // key's buffer descriptor is provably uniform (a descriptor the compiler
+  // sees in vector registers costs a waterfall loop around every load)
+  ct = uniform_ptr(ct);
+  bsk = uniform_ptr(bsk);
   const Tab key(bsk), fwd_tw(a.fwd_tw), inv_tw(a.inv_tw), post(a.post);
-  const uint32_t* v = (job % a.nlut) == 0 ? a.tpoly0 : a.tpoly1;
+  const uint32_t* v = lut == 0 ? a.tpoly0 : a.tpoly1;
   // the accumulator polynomials this group decomposes and updates
   constexpr int NC = W == 1 ? 2 : 1;
   const int c0 = W == 1 ? 0 : grp;
@@ -246,7 +254,6 @@ blind_rotate_kernel(BrArgs a) {
   uint32_t* out;
   uint32_t plain = 0u;
   if (a.out0) {
-    const uint32_t lut = (uint32_t)(job % a.nlut);
     out = (lut == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
     plain = a.plain_b[lut];
   } else {
