@@ -1,0 +1,71 @@
+"""Code-generation checks of the blind-rotation kernels for gfx950 (CPU only:
+hipcc cross-compiles).  They guard properties the throughput depends on and
+that a harmless-looking source change can lose without any parity test
+noticing:
+  * the N = 1024 kernels fit two waves per SIMD without scratch;
+  * no buffer load of the key or the transform tables sits in a waterfall
+    loop (a descriptor the compiler cannot prove uniform is re-read lane by
+    lane around every load: readfirstlane + 64-bit compare + exec loop)."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2309_09025_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
+
+
+@pytest.fixture(scope="module")
+def compiled(tmp_path_factory):
+    from paper_2309_09025_amd import build as B
+    out = tmp_path_factory.mktemp("codegen")
+    asm = str(out / "pbs.s")
+    flags = [f for f in B.FLAGS if f not in ("-fPIC",)]
+    r = subprocess.run([HIPCC, *flags, "--cuda-device-only", "-S", "-x", "hip",
+                        "-Rpass-analysis=kernel-resource-usage",
+                        os.path.join(CSRC, "pbs.hip"), "-o", asm],
+                       capture_output=True, text=True, check=True)
+    usage = {}
+    name = None
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            usage[name] = {}
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+)", line)
+        if name and m:
+            usage[name][m.group(1).strip()] = int(m.group(2))
+    with open(asm) as fh:
+        text = fh.read()
+    return usage, text
+
+
+def _br(usage, args):
+    """Resource record of blind_rotate_kernel<args...>."""
+    mangled = "_ZN2fs19blind_rotate_kernelI" + "".join(f"Li{a}E" for a in args) + "EEvNS_6BrArgsE"
+    assert mangled in usage, sorted(k for k in usage if "blind_rotate" in k)
+    return mangled, usage[mangled]
+
+
+@pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1), (10, 3, 7, 1, 1, 2, 1),
+                                  (10, 3, 7, 1, 1, 2, 2)])
+def test_n1024_kernels_two_waves_no_scratch(compiled, args):
+    usage, _ = compiled
+    _, u = _br(usage, args)
+    assert u.get("ScratchSize", 0) == 0, u
+    assert u.get("Occupancy", 0) >= 2, u
+
+
+def test_no_waterfall_loops_in_blind_rotation(compiled):
+    usage, text = compiled
+    for name in (k for k in usage if "blind_rotate_kernel" in k):
+        body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
+        # a waterfall loop compares a readfirstlane'd 64-bit value with the
+        # vector register it came from
+        assert "v_cmp_eq_u64" not in body, name
