@@ -625,7 +625,7 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   if (dk->device != ctx->device)
     return fail(FS_EPARAM, "fs_pbs_lif_ks_first: key lives on another device");
   if (B > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ks_first: batch too large");
-  if (spike2_out == v_out) return fail(FS_EINVAL, "fs_pbs_lif_ks_first: the two outputs alias");
+  if (B && spike2_out == v_out) return fail(FS_EINVAL, "fs_pbs_lif_ks_first: the two outputs alias");
   const fs_params& P = dk->prm;
   std::vector<int32_t> fire(P.p), reset(P.p);
   int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
