@@ -52,5 +52,26 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+C_CLIENT_SRC = os.path.join(ROOT, "tests", "c_abi_roundtrip.c")
+C_CLIENT = os.path.join(ROOT, "tests", "c_abi_roundtrip")
+
+
+def build_c_client(verbose: bool = True) -> str:
+    """Compile the plain-C client of the library (include/fhesnn.h + the HIP
+    runtime only) that a GPU test runs; it finds libfhesnn.so by rpath."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    out = C_CLIENT + ".tmp"
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra",
+                           "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(rocm, "include"), C_CLIENT_SRC, "-o", out,
+                           "-L", HERE, "-lfhesnn", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+                           "-Wl,-rpath," + HERE, "-Wl,-rpath,$ORIGIN/../paper_2309_09025_amd"])
+    os.replace(out, C_CLIENT)
+    if verbose:
+        print(f"built {C_CLIENT}", file=sys.stderr)
+    return C_CLIENT
+
+
 if __name__ == "__main__":
     build()
+    build_c_client()

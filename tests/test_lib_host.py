@@ -110,3 +110,14 @@ def test_range_check_theorem_4_1():
     x, Wt = cfg.data()
     M, ok = F.lif_range_check(cfg.vth, cfg.tau, 32, Wt, 0, cfg.x_max)
     assert not ok  # the tiny LIF workload wraps mod p (it is evaluated mod p)
+
+
+def test_header_is_plain_c99():
+    """include/fhesnn.h on its own compiles as strict C99 (no HIP headers)."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-fsyntax-only", "-I", os.path.join(root, "include"),
+                        os.path.join(root, "tests", "c_header_only.c")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
