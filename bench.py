@@ -240,16 +240,18 @@ def tiny_lif(F, NW, synth, ctx, dk, sk, reps=5):
 
 
 def lif_orders(F, synth, ctx, dk, sk, neurons=2048, reps=3):
-    """One LIF activation of 2048 neurons (4096 blind rotations) in the two
-    orders: key switch after each rotation (fs_pbs_lif, 4096 key switches,
-    outputs under s) and key switch first (fs_pbs_lif_ks_first, 2048 key
-    switches, outputs under z with blind-rotation noise only)."""
+    """One LIF activation of 2048 neurons in three forms: key switch after
+    each of the 4096 rotations (fs_pbs_lif, outputs under s), key switch
+    first (fs_pbs_lif_ks_first, 2048 key switches, outputs under z with
+    blind-rotation noise only), and Fire and Reset from one rotation per
+    neuron (fs_pbs_lif_many_lut, 2048 rotations, doubled rounding error)."""
     import torch
     P = dk.params
     m = synth.messages(synth.SEED_DATA, neurons, P.p, stream=91)
     out = {}
     for name, enc, width, fn in (("ks_after", F.encrypt, P.n + 1, F.pbs_lif),
-                                 ("ks_first", F.encrypt_z, P.N + 1, F.pbs_lif_ks_first)):
+                                 ("ks_first", F.encrypt_z, P.N + 1, F.pbs_lif_ks_first),
+                                 ("one_rotation", F.encrypt, P.n + 1, F.pbs_lif_many_lut)):
         h = F.to_device(enc(sk, m, synth.SEED_ENC, 70000))
         s2 = torch.zeros((neurons, width), dtype=torch.int32, device="cuda")
         vv = torch.zeros_like(s2)
@@ -260,10 +262,9 @@ def lif_orders(F, synth, ctx, dk, sk, neurons=2048, reps=3):
             fn(ctx, dk, 4, 2, h, s2, vv)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps * 1e3
-        out[name] = {"ms": round(ms, 3), "pbs_per_s": round(2 * neurons / ms * 1e3, 1),
+        out[name] = {"ms": round(ms, 3), "neurons_per_s": round(neurons / ms * 1e3, 1),
                      "output_words": width}
-    out["workload"] = (f"one LIF activation of {neurons} neurons (Fire + Reset = "
-                       f"{2 * neurons} blind rotations), N={P.N}")
+    out["workload"] = (f"one LIF activation of {neurons} neurons (Fire + Reset), N={P.N}")
     return out
 
 

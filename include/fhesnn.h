@@ -145,6 +145,14 @@ FS_API int fs_test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v_ou
 FS_API int fs_test_poly_mspace(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f,
                                uint32_t* v_out);
 
+/* Test polynomial holding two program functions for a rotation by even
+ * exponents only (fs_pbs_lif_many_lut): coefficient 2u carries f0 and
+ * 2u + 1 carries f1 of the message round(u p / N) (ties up):
+ * v_{2u+r} = Delta f_r(floor((u p + N/2) / N) mod p), u < N/2.  Both f0
+ * and f1 must satisfy f(r + p/2) = -f(r) mod p.  p <= N. */
+FS_API int fs_test_poly_two(uint32_t N, uint32_t p, const int32_t* f0, const int32_t* f1,
+                            uint32_t* v_out);
+
 /* FHE-Fire and FHE-Reset program functions (Sec. 4.2) as residue tables:
  * fire[r] = +1 if (r - V_th) mod p < p/2 else -1;
  * reset[r] = leak(r) on [0, V_th), 0 on [V_th, p/2), -leak(r - p/2) on
@@ -249,6 +257,20 @@ FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const
 FS_API int fs_pbs_mspace(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, uint32_t p_in,
                          uint32_t p_out, const uint32_t* in, size_t B, uint32_t* out,
                          int keyswitch, void* stream);
+
+/* The LIF activation with FHE-Fire and FHE-Reset (Sec. 4.2) read from ONE
+ * blind rotation instead of two: the test polynomial interleaves the two
+ * tables (fs_test_poly_two), the phase is rounded to even exponents of
+ * X (i.e. to Z_N instead of Z_2N), and coefficients 0 and 1 of the
+ * rotated accumulator are extracted and key-switched.  Half the blind
+ * rotations of fs_pbs_lif, but the modulus-switching error doubles, so
+ * decryption margins shrink (at N = 1024, p = 32 the input window is
+ * 3.1 standard deviations of that error instead of 6.2).  A different
+ * computation from fs_pbs_lif: the outputs are not the same ciphertexts.
+ * Needs p <= N.  h, spike2_out, v_out: dev [B][n+1]; v_out may alias h. */
+FS_API int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif,
+                               const uint32_t* h, size_t B, uint32_t* spike2_out,
+                               uint32_t* v_out, void* stream);
 
 /* The LIF activation in the key-switch-first order (the bootstrapping of
  * Sec. 2.1 with its Key Switching step moved in front of the Blind

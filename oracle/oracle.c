@@ -390,20 +390,31 @@ static void or_external_product(const or_params *P, const uint32_t *tgsw, const 
  * ACC = (0, X^{-b~} v), then for i = 0..n-1:
  *   ACC <- ACC + BSK_i [x] (X^{a~_i} ACC - ACC)      (CMux)
  * with a~, b~ the inputs switched to Z_{2N}.  acc has layout [2][N]. */
-OR_API void or_blind_rotate(const or_params *P, const uint32_t *bsk, const uint32_t *v,
-                            const uint32_t *ct, uint32_t *acc) {
+/* Switch to the even exponents of Z_{2N}: 2 round(x * N / 2^32), ties up
+ * (the phase rounded to Z_N, for test polynomials that interleave two
+ * program functions). */
+OR_API uint32_t or_mod_switch_even(uint32_t x, uint32_t N) {
+  uint32_t nu = or_log2(N);
+  uint32_t r = (uint32_t)(((uint64_t)x + (1ull << (31 - nu))) % 0x100000000ull) >> (32 - nu);
+  return (2 * r) % (2 * N);
+}
+
+/* Blind rotation with the exponents from or_mod_switch (even = 0) or
+ * or_mod_switch_even (even = 1). */
+OR_API void or_blind_rotate_ms(const or_params *P, const uint32_t *bsk, const uint32_t *v,
+                               const uint32_t *ct, int even, uint32_t *acc) {
   const uint32_t N = P->N, n = P->n, rows = 2 * P->l;
   uint32_t *rot = (uint32_t *)malloc(sizeof(uint32_t) * 2 * N);
   uint32_t *diff = (uint32_t *)malloc(sizeof(uint32_t) * 2 * N);
   uint32_t *prod = (uint32_t *)malloc(sizeof(uint32_t) * 2 * N);
   int32_t *digbuf = (int32_t *)malloc(sizeof(int32_t) * P->l * N);
 
-  uint32_t bbar = or_mod_switch(ct[n], N);
+  uint32_t bbar = even ? or_mod_switch_even(ct[n], N) : or_mod_switch(ct[n], N);
   memset(acc, 0, sizeof(uint32_t) * N);
   or_mul_xpow(N, (2 * N - bbar) % (2 * N), v, acc + N);
 
   for (uint32_t i = 0; i < n; i++) {
-    uint32_t abar = or_mod_switch(ct[i], N);
+    uint32_t abar = even ? or_mod_switch_even(ct[i], N) : or_mod_switch(ct[i], N);
     if (abar == 0) continue; /* X^0 ACC - ACC = 0: every digit is 0 */
     for (uint32_t c = 0; c < 2; c++) {
       or_mul_xpow(N, abar, acc + c * N, rot + c * N);
@@ -415,6 +426,11 @@ OR_API void or_blind_rotate(const or_params *P, const uint32_t *bsk, const uint3
   free(rot); free(diff); free(prod); free(digbuf);
 }
 
+OR_API void or_blind_rotate(const or_params *P, const uint32_t *bsk, const uint32_t *v,
+                            const uint32_t *ct, uint32_t *acc) {
+  or_blind_rotate_ms(P, bsk, v, ct, 0, acc);
+}
+
 /* Sample Extraction of coefficient 0: LWE_z = (a', b0) with a'_0 = a_0 and
  * a'_j = -a_{N-j} (the negacyclic reversal), so that b0 - <a', z> equals the
  * constant coefficient of the RLWE phase b(X) - a(X) z(X). */
@@ -422,6 +438,39 @@ OR_API void or_sample_extract(uint32_t N, const uint32_t *acc, uint32_t *out) {
   out[0] = acc[0];
   for (uint32_t j = 1; j < N; j++) out[j] = 0u - acc[N - j];
   out[N] = acc[N];
+}
+
+/* Sample Extraction of coefficient k: coefficient k of a(X) z(X) is
+ * sum_{j<=k} a_{k-j} z_j - sum_{j>k} a_{N+k-j} z_j, so a'_j = a_{k-j} for
+ * j <= k, a'_j = -a_{N+k-j} for j > k, and b' = b_k. */
+OR_API void or_sample_extract_at(uint32_t N, const uint32_t *acc, uint32_t k, uint32_t *out) {
+  for (uint32_t j = 0; j < N; j++) out[j] = j <= k ? acc[k - j] : 0u - acc[N + k - j];
+  out[N] = acc[N + k];
+}
+
+/* Test polynomial holding two program functions (f0, f1: Z_p -> Z_p)
+ * interleaved: with the phase on even exponents 2u of Z_{2N}, coefficient
+ * 2u carries f0 and 2u+1 carries f1 of the message round(u p / N) (ties
+ * up): v_{2u+r} = Delta f_r(floor((u p + N/2) / N) mod p), u < N/2.
+ * Both functions must be negacyclic (Theorem 2.1's condition). */
+OR_API int or_test_poly_two(uint32_t N, uint32_t p, const int32_t *f0, const int32_t *f1,
+                            uint32_t *v) {
+  const int32_t *f[2] = {f0, f1};
+  for (int r = 0; r < 2; r++)
+    for (uint32_t m = 0; m < p; m++) {
+      int64_t a = ((int64_t)f[r][(m + p / 2) % p] % p + p) % p;
+      int64_t b = ((-(int64_t)f[r][m]) % p + p) % p;
+      if (a != b) return -1;
+    }
+  const uint32_t delta = (uint32_t)(0x100000000ull / p);
+  for (uint32_t u = 0; u < N / 2; u++) {
+    uint64_t idx = ((uint64_t)u * p + N / 2) / N;
+    for (int r = 0; r < 2; r++) {
+      int64_t val = ((int64_t)f[r][idx % p] % p + p) % p;
+      v[2 * u + r] = (uint32_t)val * delta;
+    }
+  }
+  return 0;
 }
 
 /* Key Switching z -> s: round each a'_i to t*beta bits, split into t
@@ -442,6 +491,25 @@ OR_API void or_keyswitch(const or_params *P, const uint32_t *ksk, const uint32_t
       for (uint32_t w = 0; w <= n; w++) out[w] -= row[w];
     }
   }
+}
+
+/* Two bootstrappings from one blind rotation: the even-exponent rotation of
+ * a test polynomial from or_test_poly_two, then extraction of coefficients
+ * 0 (f0) and 1 (f1), each key-switched when keyswitch != 0. */
+OR_API void or_pbs_two(const or_params *P, const uint32_t *bsk, const uint32_t *ksk,
+                       const uint32_t *v, const uint32_t *ct, int keyswitch, uint32_t *out0,
+                       uint32_t *out1) {
+  const uint32_t N = P->N;
+  uint32_t *acc = (uint32_t *)malloc(sizeof(uint32_t) * 2 * N);
+  uint32_t *ext = (uint32_t *)malloc(sizeof(uint32_t) * (N + 1));
+  uint32_t *outs[2] = {out0, out1};
+  or_blind_rotate_ms(P, bsk, v, ct, 1, acc);
+  for (uint32_t k = 0; k < 2; k++) {
+    or_sample_extract_at(N, acc, k, ext);
+    if (keyswitch) or_keyswitch(P, ksk, ext, outs[k]);
+    else memcpy(outs[k], ext, sizeof(uint32_t) * (N + 1));
+  }
+  free(acc); free(ext);
 }
 
 /* bootstrapping = KeySwitch o Extract o BlindRotate o Initialize.

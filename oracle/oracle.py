@@ -80,6 +80,11 @@ def lib():
             "or_test_poly": (ctypes.c_int, [u32, u32, i32p, u32p]),
             "or_test_poly_ms": (ctypes.c_int, [u32, u32, u32, i32p, u32p]),
             "or_mod_switch": (u32, [u32, u32]),
+            "or_mod_switch_even": (u32, [u32, u32]),
+            "or_blind_rotate_ms": (None, [P, u32p, u32p, u32p, ctypes.c_int, u32p]),
+            "or_sample_extract_at": (None, [u32, u32p, u32, u32p]),
+            "or_test_poly_two": (ctypes.c_int, [u32, u32, i32p, i32p, u32p]),
+            "or_pbs_two": (None, [P, u32p, u32p, u32p, u32p, ctypes.c_int, u32p, u32p]),
             "or_gadget_digits": (None, [u32, u32, u32, i32p]),
             "or_blind_rotate": (None, [P, u32p, u32p, u32p, u32p]),
             "or_sample_extract": (None, [u32, u32p, u32p]),
@@ -295,6 +300,63 @@ def blind_rotate(keys: Keys, v, ct):
     lib().or_blind_rotate(ctypes.byref(P.c()), _u32(keys.bsk), _u32(_c(v, np.uint32)),
                           _u32(_c(ct, np.uint32)), _u32(acc))
     return acc
+
+
+def mod_switch_even(x: int, N: int) -> int:
+    return int(lib().or_mod_switch_even(int(x) & 0xFFFFFFFF, N))
+
+
+def blind_rotate_even(keys: Keys, v, ct):
+    """Blind rotation with every exponent rounded to an even one."""
+    P = keys.params
+    acc = np.zeros((2, P.N), np.uint32)
+    lib().or_blind_rotate_ms(ctypes.byref(P.c()), _u32(keys.bsk), _u32(_c(v, np.uint32)),
+                             _u32(_c(ct, np.uint32)), 1, _u32(acc))
+    return acc
+
+
+def sample_extract_at(acc, k: int):
+    acc = _c(acc, np.uint32)
+    N = acc.shape[-1]
+    out = np.zeros(N + 1, np.uint32)
+    lib().or_sample_extract_at(N, _u32(acc), k, _u32(out))
+    return out
+
+
+def test_poly_two(N: int, p: int, f0, f1):
+    """Two program functions interleaved in one test polynomial."""
+    v = np.zeros(N, np.uint32)
+    rc = lib().or_test_poly_two(N, p, _i32(_c(f0, np.int32)), _i32(_c(f1, np.int32)), _u32(v))
+    if rc != 0:
+        raise ValueError("program function is not negacyclic: f(r+p/2) != -f(r)")
+    return v
+
+
+def pbs_two_from_one(keys: Keys, v, cts, keyswitch: bool = True, nthreads=None):
+    """Both functions of a test_poly_two polynomial from one blind rotation
+    per row: returns (out0, out1)."""
+    P = keys.params
+    cts = _c(np.atleast_2d(cts), np.uint32)
+    v = _c(v, np.uint32)
+    dim = (P.n + 1) if keyswitch else (P.N + 1)
+    out = np.zeros((2, cts.shape[0], dim), np.uint32)
+    L = lib()
+    pc = P.c()
+
+    def one(k):
+        L.or_pbs_two(ctypes.byref(pc), _u32(keys.bsk), _u32(keys.ksk), _u32(v), _u32(cts[k]),
+                     1 if keyswitch else 0, _u32(out[0, k]), _u32(out[1, k]))
+    _pmap(one, range(cts.shape[0]), nthreads)
+    return out[0], out[1]
+
+
+def lif_step_one_rotation(keys: Keys, vth: int, tau: int, h, nthreads=None):
+    """The LIF activation with Fire and Reset read from one blind rotation
+    (their tables interleaved in one test polynomial): (LWE(2S), LWE(V'))."""
+    P = keys.params
+    v = test_poly_two(P.N, P.p, lut_fire(P.p, vth), lut_reset(P.p, vth, tau))
+    s, r = pbs_two_from_one(keys, v, _c(np.atleast_2d(h), np.uint32), True, nthreads)
+    return add_plain(P.p, s, 1), r
 
 
 def sample_extract(acc):

@@ -212,6 +212,34 @@ int get_tpoly(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f, uint32_t** 
   return FS_OK;
 }
 
+// device test polynomial holding two interleaved residue tables (cached)
+int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const int32_t* f1,
+                  uint32_t** out) {
+  std::vector<int32_t> key(f0, f0 + p);
+  key.insert(key.end(), f1, f1 + p);
+  key.push_back((int32_t)N);
+  key.push_back((int32_t)p);
+  key.push_back(-2);  // marks the interleaved form
+  auto it = ctx->tpoly.find(key);
+  if (it != ctx->tpoly.end()) {
+    *out = it->second;
+    return FS_OK;
+  }
+  std::vector<uint32_t> v(N);
+  int rc = test_poly_two(N, p, f0, f1, v.data());
+  if (rc) return rc;
+  uint32_t* d = nullptr;
+  FS_HIP(hipMalloc(&d, N * sizeof(uint32_t)));
+  hipError_t e = hipMemcpy(d, v.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "upload test polynomial");
+  }
+  ctx->tpoly.emplace(std::move(key), d);
+  *out = d;
+  return FS_OK;
+}
+
 // blind rotation of jobs = B * nlut, then key switch (or not)
 int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nlut,
             const uint32_t* in, size_t B, uint32_t* out0, uint32_t* out1,
@@ -374,6 +402,14 @@ int fs_test_poly_mspace(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t
                 "fs_test_poly_mspace: N, p_in, p_out must be powers of two, p_in <= 2N, "
                 "p_out <= 2^31");
   return test_poly_ms(N, p_in, p_out, f, v_out);
+}
+
+int fs_test_poly_two(uint32_t N, uint32_t p, const int32_t* f0, const int32_t* f1,
+                     uint32_t* v_out) {
+  if (!f0 || !f1 || !v_out) return fail(FS_EINVAL, "fs_test_poly_two: null argument");
+  if (!pow2_in(N, 4, 1u << 20) || !pow2_in(p, 2, N))
+    return fail(FS_EINVAL, "fs_test_poly_two: N and p must be powers of two with p <= N");
+  return test_poly_two(N, p, f0, f1, v_out);
 }
 
 int fs_lif_luts(const fs_lif* lif, uint32_t p, int32_t* fire, int32_t* reset) {
@@ -616,6 +652,63 @@ int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32
   if (rc) return rc;
   const uint32_t add[2] = {delta_of(p), 0u};  // 2S = bootstrap_Fire + 1
   return run_pbs(ctx, dk, tp, 2, h, B, spike2_out, v_out, add, 1, as_stream(stream));
+}
+
+int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h,
+                        size_t B, uint32_t* spike2_out, uint32_t* v_out, void* stream) {
+  if (!ctx || !dk || !lif || (B && (!h || !spike2_out || !v_out)))
+    return fail(FS_EINVAL, "fs_pbs_lif_many_lut: null argument");
+  if (dk->device != ctx->device)
+    return fail(FS_EPARAM, "fs_pbs_lif_many_lut: key lives on another device");
+  if (B > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_many_lut: batch too large");
+  const fs_params& P = dk->prm;
+  if (P.p > P.N) return fail(FS_ENOTSUP, "fs_pbs_lif_many_lut: needs p <= N");
+  std::vector<int32_t> fire(P.p), reset(P.p);
+  int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  uint32_t* tp = nullptr;
+  rc = get_tpoly_two(ctx, P.N, P.p, fire.data(), reset.data(), &tp);
+  if (rc) return rc;
+  if (B == 0) return FS_OK;
+  hipStream_t st = as_stream(stream);
+  // one rotation per neuron; coefficients 0 (Fire) and 1 (Reset) extracted
+  // into rows 2 g and 2 g + 1, then key-switched like a two-function batch
+  rc = ensure_ext(ctx, 2 * B * (size_t)(P.N + 1));
+  if (rc) return rc;
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  BrArgs br{};
+  br.in = h;
+  br.tpoly0 = tp;
+  br.tpoly1 = tp;
+  br.nlut = 1;
+  br.even = 1;
+  br.n = P.n;
+  br.bsk = dk->bsk;
+  br.fwd_tw = dk->fwd_tw;
+  br.inv_tw = dk->inv_tw;
+  br.post = dk->post;
+  br.uni = dk->uni;
+  br.ext = ctx->ext;
+  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, B <= ctx->split_max_jobs, st),
+                 "blind rotation");
+  if (rc) return rc;
+  KsArgs ks{};
+  ks.in = ctx->ext;
+  ks.ksk = dk->ksk;
+  ks.kskp = dk->kskp;
+  ks.out0 = spike2_out;
+  ks.out1 = v_out;
+  ks.plain_add[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
+  ks.plain_add[1] = 0u;
+  ks.nlut = 2;
+  ks.n = P.n;
+  ks.N = P.N;
+  ks.t = P.ks_t;
+  ks.beta = P.ks_base_bit;
+  return launch_rc(launch_keyswitch(ks, 2 * B, st), "key switch");
 }
 
 int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h,

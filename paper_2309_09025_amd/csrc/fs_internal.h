@@ -62,6 +62,7 @@ void encrypt(const Secret& sk, const int32_t* m, size_t count, uint64_t seed, ui
 int decrypt(const Secret& sk, const uint32_t* ct, size_t count, uint32_t dim, int32_t* m);
 int test_poly(uint32_t N, uint32_t p, const int32_t* f, uint32_t* v);
 int test_poly_ms(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f, uint32_t* v);
+int test_poly_two(uint32_t N, uint32_t p, const int32_t* f0, const int32_t* f1, uint32_t* v);
 void lif_luts(const fs_lif& lif, uint32_t p, int32_t* fire, int32_t* reset);
 
 }  // namespace fs

@@ -235,6 +235,25 @@ int test_poly_ms(uint32_t N, uint32_t p_in, uint32_t p_out, const int32_t* f, ui
   return FS_OK;
 }
 
+// Two functions in one test polynomial, for a rotation by even exponents
+// only: coefficient 2u carries f0 and 2u + 1 carries f1 of the message at
+// phase 2u / 2N, round(u p / N) with ties up.
+int test_poly_two(uint32_t N, uint32_t p, const int32_t* f0, const int32_t* f1, uint32_t* v) {
+  const uint32_t mask = p - 1;
+  const int32_t* f[2] = {f0, f1};
+  for (int k = 0; k < 2; ++k)
+    for (uint32_t r = 0; r < p; ++r)
+      if ((((uint32_t)f[k][(r + p / 2) & mask] + (uint32_t)f[k][r]) & mask) != 0)
+        return fail(FS_EINVAL, "program function violates f(r + p/2) = -f(r) (Theorem 2.1)");
+  const uint32_t delta = delta_of(p);
+  for (uint32_t u = 0; u < N / 2; ++u) {
+    const uint32_t msg = (uint32_t)(((uint64_t)u * p + N / 2) / N) & mask;
+    v[2 * u] = ((uint32_t)f0[msg] & mask) * delta;
+    v[2 * u + 1] = ((uint32_t)f1[msg] & mask) * delta;
+  }
+  return FS_OK;
+}
+
 static int32_t leak_of(int32_t h, uint32_t tau) {
   if (tau == 0) return h;  // IF: no leak
   // (tau-1)/tau * h rounded half up = floor((2 (tau-1) h + tau) / (2 tau)), h >= 0

@@ -49,6 +49,11 @@ struct BrArgs {
   uint32_t* out0;
   uint32_t* out1;
   uint32_t plain_b[2];
+  // two functions from one rotation: exponents rounded to even values, the
+  // test polynomial interleaves function 0 (even coefficients) and 1 (odd);
+  // coefficients 0 and 1 are extracted, to ext rows 2 job and 2 job + 1
+  // (or routed as functions 0 and 1).  nlut must be 1.
+  uint32_t even;
   UniTw uni;              // roots shared by all threads (scalar operands)
   // multi-key launch: per-range inputs and keys (in and bsk unused)
   const JobRange* ranges;

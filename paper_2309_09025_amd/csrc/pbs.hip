@@ -123,9 +123,14 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
   for (int j = 1; j <= L; ++j) off += HALF << (32 - j * BG);
 
+  // modulus switch: round to Z_2N, or to its even elements (Z_N doubled)
+  const uint32_t even = __builtin_amdgcn_readfirstlane(a.even);
+  const uint32_t msh = 32 - NU + even, mhalf = 1u << (msh - 1);
+  auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
+
   // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
   {
-    const uint32_t bbar = (ct[n] + (1u << (31 - NU))) >> (32 - NU);
+    const uint32_t bbar = mod_switch(ct[n]);
     const uint32_t e = (2 * N - bbar) & (2 * N - 1);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -143,7 +148,7 @@ blind_rotate_kernel(BrArgs a) {
   poly_sync<TP>();
 
   for (uint32_t i = 0; i < n; ++i) {
-    const uint32_t abar = (ct[i] + (1u << (31 - NU))) >> (32 - NU);
+    const uint32_t abar = mod_switch(ct[i]);
     if (abar == 0) continue;  // X^0 ACC - ACC = 0: every digit is zero
     double p0[LIMBS][16], p1[LIMBS][16], xd[16];
 #pragma unroll
@@ -250,22 +255,30 @@ blind_rotate_kernel(BrArgs a) {
   }
   if constexpr (W == 2) __syncthreads();  // the extraction reads both accumulators
 
-  // Sample Extraction of coefficient 0 (negacyclic reversal of the mask)
-  uint32_t* out;
-  uint32_t plain = 0u;
-  if (a.out0) {
-    out = (lut == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
-    plain = a.plain_b[lut];
-  } else {
-    out = a.ext + job * (size_t)(N + 1);
-  }
+  // Sample Extraction of coefficient k (negacyclic reversal of the mask):
+  // a'_j = a_{k-j} for j <= k, -a_{N+k-j} otherwise; b' = b_k.  Coefficient
+  // 0 always, coefficient 1 too when two functions share the rotation.
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < 16 / W; ++r) {
-    const int j = tid + W * TP * r;
-    out[j] = j == 0 ? acc[0][0] : 0u - acc[0][N - j];
+  for (uint32_t k = 0; k < 2; ++k) {
+    if (k > even) break;
+    const uint32_t fn = even ? k : lut;  // program function of this output
+    uint32_t* out;
+    uint32_t plain = 0u;
+    if (a.out0) {
+      out = (fn == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
+      plain = a.plain_b[fn];
+    } else {
+      out = a.ext + (even ? 2 * job + k : job) * (size_t)(N + 1);
+    }
+    out = uniform_ptr(out);
+#pragma unroll
+    for (int r = 0; r < 16 / W; ++r) {
+      const int j = tid + W * TP * r;
+      out[j] = j <= (int)k ? acc[0][k - j] : 0u - acc[0][N + k - j];
+    }
+    if (tid == 0) out[N] = acc[1][k] + plain;
   }
-  if (tid == 0) out[N] = acc[1][0] + plain;
 }
 
 // ---------------------------------------------------------------------------

@@ -75,6 +75,7 @@ SIGNATURES = {
     "fs_evk_free": (None, [_vp]),
     "fs_test_poly": (_int, [_u32, _u32, _i32p, _u32p]),
     "fs_test_poly_mspace": (_int, [_u32, _u32, _u32, _i32p, _u32p]),
+    "fs_test_poly_two": (_int, [_u32, _u32, _i32p, _i32p, _u32p]),
     "fs_lif_luts": (_int, [_LP, _u32, _i32p, _i32p]),
     "fs_lif_range_check": (_int, [_LP, _u32, _i32p, _sz, _sz, _i32, _i32, _i64p]),
     "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
@@ -94,6 +95,7 @@ SIGNATURES = {
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_mspace": (_int, [_vp, _vp, _i32p, _u32, _u32, _vp, _sz, _vp, _int, _vp]),
+    "fs_pbs_lif_many_lut": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ks_first": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
@@ -249,6 +251,16 @@ def test_poly_mspace(N: int, p_in: int, p_out: int, f) -> np.ndarray:
     return v
 
 
+def test_poly_two(N: int, p: int, f0, f1) -> np.ndarray:
+    f0, p0 = _np_i32(f0)
+    f1, p1 = _np_i32(f1)
+    if f0.size != p or f1.size != p:
+        raise ValueError(f"test_poly_two: both functions need p = {p} entries")
+    v = np.zeros(N, np.uint32)
+    _check("fs_test_poly_two", lib().fs_test_poly_two(N, p, p0, p1, v.ctypes.data_as(_u32p)))
+    return v
+
+
 def lif_luts(v_th: int, tau: int, p: int):
     fire = np.zeros(p, np.int32)
     reset = np.zeros(p, np.int32)
@@ -390,6 +402,20 @@ def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
     lif = CLif(v_th, tau)
     _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
                                           _dptr(spike2_out), _dptr(v_out), _stream(stream)))
+
+
+def pbs_lif_many_lut(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
+                     stream=None):
+    """Fire and Reset from one blind rotation per neuron: h, spike2_out,
+    v_out are [B][n+1]."""
+    w = dk.params.n + 1
+    for name, t in (("h", h), ("spike2_out", spike2_out), ("v_out", v_out)):
+        if t.dim() != 2 or t.shape[1] != w or t.shape[0] != h.shape[0]:
+            raise ValueError(f"pbs_lif_many_lut: {name} must be [{h.shape[0]}][{w}]")
+    lif = CLif(v_th, tau)
+    _check("fs_pbs_lif_many_lut",
+           lib().fs_pbs_lif_many_lut(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
+                                     _dptr(spike2_out), _dptr(v_out), _stream(stream)))
 
 
 def pbs_lif_ks_first(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,

@@ -210,6 +210,30 @@ def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, co
         assert wrong <= 1, wrong
 
 
+@pytest.mark.parametrize("shape,count,split", [(0, 1, True), (0, 37, True), (0, 37, False),
+                                               (0, 1100, False), (1, 3, True), (1, 5, False)])
+def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, split):
+    """Fire and Reset from one even-exponent rotation per neuron (one- and
+    two-group kernels, ragged batches, both shapes): sampled neurons equal
+    the oracle's."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(shape)
+    ok = okeys_a if shape == 0 else okeys_b
+    m = synth.messages(synth.SEED_DATA, count, P.p, stream=870 + count)
+    h = F.encrypt(sk, m, synth.SEED_ENC, 64000 + 1000 * shape + count)
+    s2 = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
+    vv = torch.zeros_like(s2)
+    prev = ctx.set_split(1 << 20 if split else 0)
+    try:
+        F.pbs_lif_many_lut(ctx, dk, 4, 2, _dev(h), s2, vv)
+    finally:
+        ctx.set_split(prev)
+    idx = sorted({0, count // 2, count - 1})
+    spikes, vnew = O.lif_step_one_rotation(ok, 4, 2, h[idx])
+    assert np.array_equal(_host(s2)[idx], spikes)
+    assert np.array_equal(_host(vv)[idx], vnew)
+
+
 def test_pbs_lif_key_switch_first_output_may_alias_input(gpu_env, okeys_a):
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)

@@ -79,6 +79,12 @@ def test_message_space_test_poly_matches_oracle(N, p_in, p_out):
         F.test_poly_mspace(N, 4 * N, p_out, np.zeros(4 * N, np.int32))  # p_in > 2N
 
 
+@pytest.mark.parametrize("N,p", [(1024, 32), (2048, 64), (1024, 16)])
+def test_interleaved_test_poly_matches_oracle(N, p):
+    fire, reset = F.lif_luts(4, 2, p)
+    assert np.array_equal(F.test_poly_two(N, p, fire, reset), O.test_poly_two(N, p, fire, reset))
+
+
 def test_errors_are_reported_not_raised_in_c():
     bad = O.lut_reset(32, 4, 2).copy()
     bad[17] = 15  # the printed fourth branch p/2 - leak: not negacyclic

@@ -4,6 +4,7 @@ brute force on tiny inputs.  CPU only."""
 import ctypes
 import math
 import os
+from dataclasses import replace
 from fractions import Fraction
 
 import numpy as np
@@ -255,6 +256,53 @@ def test_sample_extract_phase():
     _, z = O.secret_keys(O.SHAPE_A, 3)
     ext = O.sample_extract(acc)
     assert O.phase(z, ext)[0] == _rlwe_phase(acc, z)[0]
+
+
+def test_sample_extract_at_phase():
+    """Extraction of coefficient k: the LWE phase is coefficient k of the
+    RLWE phase, for every k (including 0 and N-1)."""
+    N = 1024
+    g = synth.rng(18)
+    acc = g.integers(0, U32, size=(2, N), dtype=np.uint64).astype(np.uint32)
+    _, z = O.secret_keys(O.SHAPE_A, 3)
+    ph = _rlwe_phase(acc, z)
+    for k in (0, 1, 2, 511, N - 1):
+        assert O.phase(z, O.sample_extract_at(acc, k))[0] == ph[k], k
+    assert np.array_equal(O.sample_extract_at(acc, 0), O.sample_extract(acc))
+
+
+def test_mod_switch_even_is_doubled_rounding_to_z_n():
+    N = 1024
+    g = synth.rng(19)
+    xs = list(g.integers(0, U32, size=200, dtype=np.uint64)) + [0, U32 - 1, 1 << 21, (1 << 21) - 1,
+                                                              (1 << 22) + (1 << 21), 1 << 31]
+    for x in xs:
+        r = math.floor(Fraction(int(x) * N, U32) + Fraction(1, 2)) % N
+        assert O.mod_switch_even(int(x), N) == 2 * r, x
+
+
+def test_test_poly_two_hand_example():
+    """N = 8, p = 4: u = 0..3 carries message floor((4u + 4) / 8) = 0, 1, 1, 2;
+    f0 = (1, 2, -1, -2) on even and f1 = (0, 1, 0, -1) on odd coefficients,
+    times Delta = 2^30."""
+    v = O.test_poly_two(8, 4, [1, 2, -1, -2], [0, 1, 0, -1])
+    assert [int(x) for x in v] == [x * 2 ** 30 for x in (1, 0, 2, 1, 2, 1, 3, 0)]
+    with pytest.raises(ValueError):
+        O.test_poly_two(8, 4, [1, 2, -1, -2], [0, 1, 1, -1])
+
+
+def test_one_rotation_computes_both_functions(okeys_a):
+    """Fire and Reset interleaved in one test polynomial and read from one
+    even-exponent blind rotation decrypt to both functions of every message
+    (p = 16, so that the doubled modulus-switching error keeps a 6-sigma
+    margin; the keys do not depend on p)."""
+    P = replace(O.SHAPE_A, p=16)
+    K = O.Keys(P, okeys_a.s, okeys_a.z, okeys_a.bsk, okeys_a.ksk)
+    m = np.arange(-P.p // 2 + 1, P.p // 2 + 1, dtype=np.int32)
+    ct = O.encrypt(P, K.s, m, 12)
+    s2, v = O.lif_step_one_rotation(K, 4, 2, ct)
+    assert list(O.decrypt(P.p, K.s, s2)) == list(O.centred(P.p, O.plain_fire(P.p, 4, m)))
+    assert list(O.decrypt(P.p, K.s, v)) == list(O.centred(P.p, O.plain_reset(P.p, 4, 2, m)))
 
 
 def test_keyswitch_rounding_bound():
