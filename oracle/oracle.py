@@ -499,12 +499,14 @@ def zero_ct(count: int, dim1: int):
 
 
 def lif_layer_run(keys: Keys, I_ct, vth: int, tau: int, T: int, nthreads=None,
-                  ks_first: bool = False):
+                  ks_first: bool = False, one_rotation: bool = False):
     """One LIF layer driven by a static input current LWE(I) for T steps:
     H[t] = V[t-1] + I; (2S[t], V[t]) = (FHE-Fire(H) + 1, FHE-Reset(H)).
     Returns lists (per step) of H, 2S and V ciphertexts.  ks_first: the
-    ciphertexts are under z and each step uses lif_step_ks_first."""
-    step = lif_step_ks_first if ks_first else lif_step
+    ciphertexts are under z and each step uses lif_step_ks_first;
+    one_rotation: each step uses lif_step_one_rotation."""
+    step = (lif_step_ks_first if ks_first else
+            lif_step_one_rotation if one_rotation else lif_step)
     V = zero_ct(I_ct.shape[0], I_ct.shape[1])
     Hs, Ss, Vs = [], [], []
     for _ in range(T):

@@ -64,13 +64,16 @@ class LifLayerNet:
     """One LIF layer fed by a static current I = W x (the tiny LIF workload).
 
     ks_first: the key-switch-first order (fs_pbs_lif_ks_first); inputs and
-    states are then ciphertexts under z, [.][N+1]."""
+    states are then ciphertexts under z, [.][N+1].  many_lut: Fire and Reset
+    from one blind rotation (fs_pbs_lif_many_lut)."""
 
     def __init__(self, ctx, dk, W: np.ndarray, lif: LifSpec = LifSpec(), capture: bool = False,
-                 ks_first: bool = False):
+                 ks_first: bool = False, many_lut: bool = False):
         self.ctx, self.dk, self.lif = ctx, dk, lif
         P = dk.params
-        self.ks_first = ks_first
+        if ks_first and many_lut:
+            raise ValueError("choose one of ks_first and many_lut")
+        self.ks_first, self.many_lut = ks_first, many_lut
         self.width = (P.N if ks_first else P.n) + 1
         self.W = F.to_device(np.ascontiguousarray(W, np.int32))
         self.O = W.shape[0]
@@ -85,7 +88,8 @@ class LifLayerNet:
 
     def _step(self):
         F.lwe_add(self.ctx, self.V, self.I, self.H)
-        act = F.pbs_lif_ks_first if self.ks_first else F.pbs_lif
+        act = (F.pbs_lif_ks_first if self.ks_first else
+               F.pbs_lif_many_lut if self.many_lut else F.pbs_lif)
         act(self.ctx, self.dk, self.lif.v_th, self.lif.tau, self.H, self.S, self.V)
 
     def run(self, x_ct: torch.Tensor, T: int, record: bool = True):

@@ -56,6 +56,25 @@ def test_tiny_lif_layer_key_switch_first_bit_exact(gpu_env, okeys_a, capture):
         assert np.array_equal(F.decrypt(sk, V), O.centred(P.p, pV[t])), t
 
 
+@pytest.mark.parametrize("capture", [False, True])
+def test_tiny_lif_layer_many_lut_bit_exact(gpu_env, okeys_a, capture):
+    """The tiny LIF layer with Fire and Reset read from one blind rotation per
+    neuron and step: bit-exact against the oracle's same form."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.TinyLIF()
+    x, W = cfg.data()
+    ct = F.encrypt(sk, x, synth.SEED_ENC)
+    net = NW.LifLayerNet(ctx, dk, W, NW.LifSpec(cfg.vth, cfg.tau), capture=capture,
+                         many_lut=True)
+    got = net.run(F.to_device(ct), cfg.T)
+    I_ct = O.lwe_linear(W, O.encrypt(O.SHAPE_A, okeys_a.s, x, synth.SEED_ENC))
+    Hs, Ss, Vs = O.lif_layer_run(okeys_a, I_ct, cfg.vth, cfg.tau, cfg.T, one_rotation=True)
+    for t in range(cfg.T):
+        H, S, V = got[t]
+        assert np.array_equal(H, Hs[t]) and np.array_equal(S, Ss[t]) and np.array_equal(V, Vs[t]), t
+
+
 @pytest.mark.parametrize("mode", ["eager", "graph", "pipelined"])
 def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     """The conv -> FC -> FC topology at a size the oracle runs end to end:
