@@ -420,9 +420,9 @@ def main():
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the bootstrappings of a batch "
-              "are independent; sharding across GPUs is described in DESIGN.md, not built)",
-              file=sys.stderr)
+        print("bench.py: runs on exactly one GPU; a multi-GPU path (independent "
+              "bootstrappings split by request or image, one all-gather of spikes per layer "
+              "for a sharded layer) is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
