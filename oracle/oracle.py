@@ -2,7 +2,7 @@
 
 Only the tests, the smoke check and the bench's CPU-baseline leg may import
 this module.  It wraps the plain C oracle in ``oracle.c`` (built with gcc by
-``build()``) and adds the network-level drivers written out in Python:
+``build()``) and adds the network-level runs written out in Python:
 
 * ``lif_step`` / ``network`` -- the encrypted LIF network, composed of the
   oracle's WeightSum (Sec. 4.1, Eq. "noise grows") and bootstrapping
@@ -35,7 +35,7 @@ GCC_FLAGS = ["-O3", "-mavx2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (the checker, not the product)."""
+    """Compile oracle.c into liboracle.so with gcc (test infrastructure, not the product)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])

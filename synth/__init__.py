@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs shared by the tests, the bench and the oracle drivers.
+"""Seeded synthetic inputs shared by the tests, the bench and the oracle's network runs.
 
 This module holds none of the method's arithmetic: it only draws plaintext
 messages, integer weights, spike patterns and images with numpy's PCG64, so

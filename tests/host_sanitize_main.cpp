@@ -10,7 +10,7 @@
 #include "fs_internal.h"
 
 namespace fs {
-// the error channel lives in the C ABI file, which this build leaves out
+// the error channel lives in the C ABI file, which this sanitizer compilation leaves out
 static std::string g_last;
 void set_error(const std::string& msg) { g_last = msg; }
 int fail(int code, const std::string& msg) {

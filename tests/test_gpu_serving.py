@@ -106,7 +106,7 @@ def test_serving_results_equal_alone_and_in_the_mix(gpu_env, clients):
         solo = SV.Request(r.rid, r.client, r.px_ct, r.T, r.hidden, 0.0)
         alone.run([solo])
         assert np.array_equal(solo.score, r.score), r.rid
-        # and the same as the single-image network driver
+        # and the same as the single-image network
         W1, W2 = alone.nets[r.hidden]
         net = NW.ConvSNN(ctx, clients[r.client][2], synth.CONV_SNN_MINI.data()[1],
                          F.to_host(W1).view(np.int32), F.to_host(W2).view(np.int32),

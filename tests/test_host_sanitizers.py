@@ -1,7 +1,7 @@
 """The library's host-side client code (key generation, encryption,
 decryption, program-function tables) built with g++ under AddressSanitizer
 and UndefinedBehaviorSanitizer and driven through both parameter sets and
-its error paths.  CPU only: the GPU code is not part of this build."""
+its error paths.  CPU only: the GPU code is not part of this compilation."""
 import os
 import shutil
 import subprocess

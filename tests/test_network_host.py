@@ -1,4 +1,4 @@
-"""Host-side logic of the network driver (no GPU): the average pool folded
+"""Host-side logic of the network code (no GPU): the average pool folded
 into the next layer's weights (Sec. 3.3) multiplies exactly the window sums
 of the unpooled spikes."""
 import numpy as np
