@@ -3,7 +3,6 @@ against the plaintext integer SNN (decrypted spikes), eagerly and with each
 timestep replayed from a captured HIP graph."""
 import numpy as np
 import pytest
-import torch
 
 import synth
 from oracle import oracle as O

@@ -8,7 +8,6 @@ noticing:
     lane around every load: readfirstlane + 64-bit compare + exec loop)."""
 import os
 import re
-import shutil
 import subprocess
 
 import pytest
