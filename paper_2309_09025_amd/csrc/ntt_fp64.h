@@ -305,11 +305,13 @@ __device__ __forceinline__ void fwd_stages_reg(double x[16], const double* w) {
   }
 }
 
-template <int LOGN>
+// Stages SHI down to LOGN-4 of round A (SHI = LOGN-2 when the caller has
+// done the first stage itself).
+template <int LOGN, int SHI = LOGN - 1>
 __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
   using S = NttShape<LOGN>;
 #pragma unroll
-  for (int s = LOGN - 1; s >= LOGN - 4; --s) {
+  for (int s = SHI; s >= LOGN - 4; --s) {
     const int b = s - S::LOA;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -330,7 +332,7 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
 // a sum of 2l products with reduced key values below 5 P < 2^53 (the bound
 // check of this schedule is in tests/test_ntt_bounds.py).  The per-thread
 // roots of rounds B and C are requested one round ahead.
-template <int LOGN>
+template <int LOGN, bool FIRST_DONE = false>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
                                             const Tab& tw, int t) {
   using S = NttShape<LOGN>;
@@ -338,7 +340,7 @@ __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const Uni
   constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
   double wb[R::FB];
   load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb, tw, t);
-  fwd_roundA_uni<LOGN>(x, u);
+  fwd_roundA_uni<LOGN, FIRST_DONE ? LOGN - 2 : LOGN - 1>(x, u);
   exchange<LOGN, S::LOA, S::LOB>(x, lds, t);
   double wc[R::FC];
   load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);

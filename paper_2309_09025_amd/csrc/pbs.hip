@@ -87,6 +87,12 @@ blind_rotate_kernel(BrArgs a) {
   static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
   __shared__ double lds_all[W][S::LDS_DOUBLES];
   __shared__ uint32_t acc[2][N];
+  // first forward stage by table: its operands are raw digits, so the
+  // products digit * psi^{brv(1)} take only 2 HALF values, one per field
+  // value f = digit + HALF, stored reduced.  Used for small digit ranges
+  // (Bg = 2^7: 128 entries); at Bg = 2^10 the 8 KiB table measured no gain.
+  constexpr bool TAB1 = 2 * HALF <= 256;
+  __shared__ double stage1[TAB1 ? 2 * HALF : 1];
 
   const int grp = W == 1 ? 0 : (int)threadIdx.x / TP;  // polynomial group
   const int t = (int)threadIdx.x - grp * TP;
@@ -127,6 +133,12 @@ blind_rotate_kernel(BrArgs a) {
   const uint32_t even = __builtin_amdgcn_readfirstlane(a.even);
   const uint32_t msh = 32 - NU + even, mhalf = 1u << (msh - 1);
   auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
+
+  if constexpr (TAB1) {
+    for (int f = threadIdx.x; f < (int)(2 * HALF); f += W * TP)
+      stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
+    if constexpr (W * TP > 64) __syncthreads();  // every wave reads the whole table
+  }
 
   // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
   {
@@ -197,10 +209,23 @@ blind_rotate_kernel(BrArgs a) {
         if constexpr (PF >= 1) load_half(0);
         if constexpr (PF == 2) load_half(1);
         const uint32_t sh = 32 - (lv + 1) * BG;
+        if constexpr (TAB1) {
+          // stage LOGN-1 pairs register r with r + 8: the upper digit times
+          // the root comes from the table
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
-        ntt_fwd_reg<LOGN>(xd, lds, a.uni, fwd_tw, t);
+          for (int r = 0; r < 8; ++r) {
+            const double x0 =
+                (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+            const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
+            xd[r + 8] = x0 - m;
+            xd[r] = x0 + m;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+        }
+        ntt_fwd_reg<LOGN, TAB1>(xd, lds, a.uni, fwd_tw, t);
         if constexpr (PF == 0) {
           load_half(0);
           mac_half(0);
