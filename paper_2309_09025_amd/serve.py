@@ -13,6 +13,11 @@ scores).
   its own client's key), so requests that arrived at different times share
   the device; WeightSum layers run per request (own widths and weights).
 * Latency = completion - arrival, on the host clock.
+* A request's state between timesteps is its step counter, its LIF
+  potentials and its score ciphertexts: `checkpoint` copies them to the host
+  and frees the device memory, `resume` (on this or another server, after a
+  restart) re-admits the request from them, and the rest of its run is
+  byte-identical to an uninterrupted one.  `cancel` drops a request.
 
 Every request's result is a deterministic function of its own inputs and
 key: it is byte-identical alone and in any mix.
@@ -97,6 +102,57 @@ class Server:
         r.bufs = b
         r.t = 0
         self.mem_used += self.request_bytes(r.hidden)
+
+    # ---------------------------------------------------------------- state
+    STATE_KEYS = ("V1", "V2", "score")
+
+    def checkpoint(self, r: Request) -> dict:
+        """Host copy of an in-flight request's state at a timestep boundary
+        (the static conv current is recomputed from the pixels on resume);
+        the request leaves the device."""
+        torch.cuda.synchronize()
+        state = {"t": r.t, "hidden": r.hidden, "client": r.client}
+        state.update({k: F.to_host(r.bufs[k]) for k in self.STATE_KEYS})
+        self.cancel(r)
+        return state
+
+    def resume(self, r: Request, state: dict):
+        """Re-admit a request from a checkpoint taken on any server with the
+        same networks and the client's key registered."""
+        if (state["hidden"], state["client"]) != (r.hidden, r.client):
+            raise ValueError("checkpoint of a different request")
+        if self.mem_used + self.request_bytes(r.hidden) > self.budget:
+            raise MemoryError("request does not fit the memory budget")
+        self._admit(r)
+        for k in self.STATE_KEYS:
+            r.bufs[k].copy_(F.to_device(state[k]))
+        r.t = int(state["t"])
+
+    def cancel(self, r: Request):
+        """Drop an in-flight request and free its device memory."""
+        if r.bufs:
+            r.bufs = {}
+            self.mem_used -= self.request_bytes(r.hidden)
+
+    def step(self, inflight):
+        """One tick over the given in-flight requests (each advances one
+        timestep); returns those that are now complete (their scores filled
+        in and their memory freed)."""
+        self._tick(inflight)
+        torch.cuda.synchronize()
+        done = []
+        for r in inflight:
+            r.t += 1
+            if r.t >= r.T:
+                self._retire(r, time.perf_counter())
+                done.append(r)
+        return done
+
+    def admit(self, r: Request):
+        """Admit a request now (budget permitting)."""
+        if self.mem_used + self.request_bytes(r.hidden) > self.budget:
+            raise MemoryError("request does not fit the memory budget")
+        self._admit(r)
 
     def _retire(self, r: Request, now: float):
         r.score = F.to_host(r.bufs["score"])

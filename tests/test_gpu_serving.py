@@ -116,3 +116,50 @@ def test_serving_results_equal_alone_and_in_the_mix(gpu_env, clients):
         assert np.array_equal(score, r.score), r.rid
     stats = SV.latency_stats(done)
     assert stats["p99_s"] >= stats["p50_s"] > 0
+
+
+def test_checkpoint_and_resume_on_another_server_is_byte_identical(gpu_env, clients):
+    """A request checkpointed after two of its four timesteps, its device
+    memory freed, and resumed on a second server with its own context (a
+    restart) finishes with the same score bits as an uninterrupted run; a
+    cancelled request releases its memory; an oversized resume is refused."""
+    ctx, _ = gpu_env
+    base = synth.CONV_SNN_MINI
+    widths = (8, 12)
+    cid, T, H = 1, 4, 12
+    sk, evk, dk = clients[cid]
+    px = synth.ConvSNN(**{**base.__dict__}).data(image_stream=7)[0]
+    ct = F.encrypt(sk, px, synth.SEED_ENC, 700000)
+
+    ref = _server(ctx, base, widths, budget=1 << 30)
+    ref.keys = {cid: dk}
+    ref.width = dk.params.n + 1
+    whole = SV.Request(0, cid, ct, T, H)
+    ref.run([whole])
+
+    first = _server(ctx, base, widths, budget=1 << 30)
+    first.keys = {cid: dk}
+    first.width = ref.width
+    r = SV.Request(1, cid, ct, T, H)
+    first.admit(r)
+    assert first.step([r]) == [] and first.step([r]) == []
+    state = first.checkpoint(r)
+    assert first.mem_used == 0 and state["t"] == 2
+
+    ctx2 = F.Context(0)  # a fresh context and key upload, as after a restart
+    second = _server(ctx2, base, widths, budget=1 << 30)
+    second.register(cid, evk)
+    r2 = SV.Request(2, cid, ct, T, H)
+    second.resume(r2, state)
+    done = []
+    while not done:
+        done = second.step([r2])
+    assert np.array_equal(r2.score, whole.score)
+
+    tiny = _server(ctx2, base, widths, budget=1)
+    tiny.keys, tiny.width = second.keys, second.width
+    with pytest.raises(MemoryError):
+        tiny.resume(SV.Request(3, cid, ct, T, H), state)
+    second.admit(r3 := SV.Request(4, cid, ct, T, H))
+    second.cancel(r3)
+    assert second.mem_used == 0
