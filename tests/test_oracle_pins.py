@@ -73,6 +73,27 @@ def test_gaussian_moments():
     assert L.or_gauss_from_words(123, 456, 0.0) == 0
 
 
+def test_decryption_failure_rate_under_inflated_noise(okeys_a):
+    """Forced noise overflow: with sigma_lwe = 2^-7 against the half window
+    1/64 = 2 sigma of p = 32, a decryption fails exactly when the Gaussian
+    error leaves (-1/64, 1/64]: probability erfc(2 / sqrt 2) = 4.55 %; the
+    measured rate over 20,000 encryptions sits inside 4 binomial standard
+    errors, and every failure is off by one message in the error's
+    direction."""
+    P = replace(O.SHAPE_A, sigma_lwe=2.0 ** -7)
+    n = 20000
+    m = synth.messages(synth.SEED_DATA, n, P.p, stream=77)
+    ct = O.encrypt(P, okeys_a.s, m, 31)
+    got = O.decrypt(P.p, okeys_a.s, ct)
+    err = _signed(O.phase(okeys_a.s, ct).astype(np.int64) - (m.astype(np.int64) % P.p) * P.delta)
+    want = math.erfc(2 / math.sqrt(2))
+    bad = got != m
+    rate = bad.mean()
+    assert abs(rate - want) < 4 * math.sqrt(want * (1 - want) / n), (rate, want)
+    step = np.sign(err[bad]).astype(np.int64)
+    assert np.array_equal(O.centred(P.p, got[bad].astype(np.int64) - m[bad] - step), np.zeros(bad.sum()))
+
+
 # ------------------------------------------------------------------ P3: negacyclic products
 
 def test_negacyclic_hand_example():
