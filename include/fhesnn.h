@@ -192,9 +192,17 @@ FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
  * functions) run each job on two groups of N/16 threads that split the
  * accumulator's two polynomials and exchange partial products once per CMux
  * step (same results; lower latency when the batch cannot fill the device).
- * Default: 4 x the device's compute units.  0 disables the split.  The
+ * Default: 3 x the device's compute units.  0 disables the split.  The
  * previous threshold is stored in *previous unless it is NULL. */
 FS_API int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous);
+
+/* Batches of at most max_jobs jobs (checked before the split threshold)
+ * run each job on 2l groups, one per digit row of the external product
+ * (Sec. 2.1, RGSW product; N = 1024): a CMux step's critical path is one
+ * forward and one inverse transform, for the lowest latency of a single
+ * bootstrapping or a few.  Same results.  Default: 2 x the device's
+ * compute units.  0 disables it.  *previous as above. */
+FS_API int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous);
 
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
  * the exact negacyclic transform on the device; the KSK is copied as is.

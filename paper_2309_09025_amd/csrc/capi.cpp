@@ -47,6 +47,7 @@ struct fs_ctx {
   // (set at creation to 4 x the device's compute units: below that the
   // one-group kernel leaves SIMDs idle)
   size_t split_max_jobs = 0;
+  size_t rows_max_jobs = 0;  // batches up to this size: one thread group per digit row
   // device copy of the range table of the last multi-key launch
   fs::JobRange* ranges = nullptr;
   size_t ranges_cap = 0;
@@ -240,6 +241,12 @@ int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const 
   return FS_OK;
 }
 
+// thread groups per job for a batch of this size (see launch_blind_rotate)
+int br_groups(const fs_ctx* ctx, size_t jobs) {
+  if (jobs <= ctx->rows_max_jobs) return kBrRows;
+  return jobs <= ctx->split_max_jobs ? kBrTwo : kBrOne;
+}
+
 // blind rotation of jobs = B * nlut, then key switch (or not)
 int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nlut,
             const uint32_t* in, size_t B, uint32_t* out0, uint32_t* out1,
@@ -248,7 +255,6 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   const size_t jobs = B * nlut;
   auto vit = ctx->br_variant.find(P.N);
   const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
-  const bool split = jobs <= ctx->split_max_jobs;
   BrArgs br{};
   br.in = in;
   br.tpoly0 = tp[0];
@@ -267,7 +273,8 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   } else {
     br.ext = out0;
   }
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, split, st), "blind rotation");
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
+                     "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
   ks.in = br.ext;
@@ -446,7 +453,10 @@ int fs_ctx_create(int device, fs_ctx** ctx) {
   FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   auto* c = new fs_ctx;
   c->device = device;
-  c->split_max_jobs = 4 * (size_t)cus;
+  // measured crossovers (4096 bootstrappings' worth of kernels, N = 1024):
+  // one group per digit row wins up to 2 jobs per CU, two groups up to 3
+  c->split_max_jobs = 3 * (size_t)cus;
+  c->rows_max_jobs = 2 * (size_t)cus;
   *ctx = c;
   return FS_OK;
 }
@@ -478,6 +488,14 @@ int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (previous) *previous = ctx->split_max_jobs;
   ctx->split_max_jobs = max_jobs;
+  return FS_OK;
+}
+
+int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (previous) *previous = ctx->rows_max_jobs;
+  ctx->rows_max_jobs = max_jobs;
   return FS_OK;
 }
 
@@ -692,7 +710,7 @@ int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.post = dk->post;
   br.uni = dk->uni;
   br.ext = ctx->ext;
-  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, B <= ctx->split_max_jobs, st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, br_groups(ctx, B), st),
                  "blind rotation");
   if (rc) return rc;
   KsArgs ks{};
@@ -767,7 +785,7 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.plain_b[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
   br.plain_b[1] = 0u;
   return launch_rc(
-      launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, st),
+      launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
       "blind rotation");
 }
 
@@ -844,7 +862,7 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   br.ext = ctx->ext;
   br.ranges = ctx->ranges;
   br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, jobs <= ctx->split_max_jobs, st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
                  "blind rotation");
   if (rc) return rc;
   // one batched key switch per key over its adjacent ranges

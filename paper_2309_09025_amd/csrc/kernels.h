@@ -79,8 +79,11 @@ struct KsArgs {
 int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
                       const double* tw, hipStream_t st);
 int blind_rotate_variants(uint32_t N);
-// split: two polynomial groups per job (small batches)
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+// Thread groups per job: 1 (large batches; `variant` picks the tuned
+// instance), 2 (one group per input polynomial) or 0 = one group per digit
+// row (2l groups, N = 1024 only; smallest batches, latency).
+enum BrGroups { kBrOne = 1, kBrTwo = 2, kBrRows = 0 };
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, int groups,
                         hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);
 // words per KSK row n+1 rounded up to the 32-word tiles of the matrix-core

@@ -307,6 +307,150 @@ blind_rotate_kernel(BrArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Blind rotation for latency (small batches): one thread group of TP threads
+// per digit row, 2l groups per job.  Group g = c l + lv rotates ACC_c,
+// extracts digit level lv, transforms it and multiplies it with its key row
+// for both outputs; the products of all rows are summed in LDS with exact
+// binary64 atomic adds (integers below 4.9 P < 2^53, so the order of the
+// additions cannot change the sum).  Groups 0 and 1 then inverse-transform
+// output 0 and 1 and update ACC.  A step's critical path is one forward and
+// one inverse transform instead of three forward and one inverse (two-group
+// form) or six and two (one group).  Same bits as blind_rotate_kernel.
+template <int LOGN, int L, int BG>
+__global__ void __launch_bounds__(2 * L * NttShape<LOGN>::TP)
+blind_rotate_rows_kernel(BrArgs a) {
+  using S = NttShape<LOGN>;
+  constexpr int N = S::N, TP = S::TP, ROWS = 2 * L, NT = ROWS * TP;
+  constexpr uint32_t HALF = 1u << (BG - 1);
+  constexpr uint32_t NU = LOGN + 1;
+  constexpr int G = 2;  // one key limb: mask and body values per slot
+  static_assert(TP == 64, "one wavefront per row");
+  __shared__ double lds_all[ROWS][S::LDS_DOUBLES];
+  __shared__ double sums[2][16 * TP];  // [output][r][t]: row products summed
+  __shared__ uint32_t acc[2][N];
+  __shared__ double stage1[2 * HALF];
+
+  const int grp = (int)threadIdx.x / TP;
+  const int t = (int)threadIdx.x - grp * TP;
+  const int c = grp / L, lv = grp % L;
+  double* lds = lds_all[grp];
+  const size_t job = blockIdx.x;
+  const uint32_t n = a.n;
+  const uint64_t g = a.nlut == 2 ? job >> 1 : job;
+  const uint32_t lut = a.nlut == 2 ? (uint32_t)(job & 1u) : 0u;
+  const uint32_t* ct;
+  const double* bsk;
+  if (a.ranges) {
+    const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+    ct = rg.in + (g - rg.first) * (size_t)(n + 1);
+    bsk = rg.bsk;
+  } else {
+    ct = a.in + g * (size_t)(n + 1);
+    bsk = a.bsk;
+  }
+  ct = uniform_ptr(ct);
+  bsk = uniform_ptr(bsk);
+  const Tab key(bsk), fwd_tw(a.fwd_tw), inv_tw(a.inv_tw), post(a.post);
+  const uint32_t* v = lut == 0 ? a.tpoly0 : a.tpoly1;
+
+  uint32_t off = 1u << (31 - L * BG);
+#pragma unroll
+  for (int j = 1; j <= L; ++j) off += HALF << (32 - j * BG);
+  const uint32_t even = __builtin_amdgcn_readfirstlane(a.even);
+  const uint32_t msh = 32 - NU + even, mhalf = 1u << (msh - 1);
+  auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
+
+  const int tid = threadIdx.x;
+  for (int f = tid; f < (int)(2 * HALF); f += NT)
+    stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
+  for (int j = tid; j < 2 * 16 * TP; j += NT) (&sums[0][0])[j] = 0.0;
+  {
+    const uint32_t bbar = mod_switch(ct[n]);
+    const uint32_t e = (2 * N - bbar) & (2 * N - 1);
+    for (int j = tid; j < N; j += NT) {
+      const int src = j - (int)e;
+      uint32_t val;
+      if (src >= 0) val = v[src];
+      else if (src + N >= 0) val = 0u - v[src + N];
+      else val = v[src + 2 * N];
+      acc[0][j] = 0u;
+      acc[1][j] = val;
+    }
+  }
+  __syncthreads();
+
+  const uint32_t sh = 32 - (lv + 1) * BG;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t abar = mod_switch(ct[i]);
+    if (abar == 0) continue;
+    // this group's key row, requested before the transform
+    const uint32_t row = i * (uint32_t)(ROWS * 16 * TP * G * 8) +
+                         (uint32_t)(grp * 16 * TP * G * 8);
+    double kv[16][G];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      key.at2((uint32_t)t * (G * 8), row + (uint32_t)(r * TP * G * 8), kv[r][0], kv[r][1]);
+    // digit level lv of D_c = X^{a~} ACC_c - ACC_c (plus the rounding offset)
+    double xd[16];
+    {
+      uint32_t d[16];
+      const uint32_t* ac = acc[c];
+      const int kb = t - (int)abar;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = kb + TP * r;
+        const uint32_t val = ac[k & (N - 1)];
+        const uint32_t neg = 0u - (((uint32_t)k >> LOGN) & 1u);
+        d[r] = ((val ^ neg) - neg) - ac[t + TP * r] + off;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double x0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+        const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
+        xd[r + 8] = x0 - m;
+        xd[r] = x0 + m;
+      }
+    }
+    ntt_fwd_reg<LOGN, true>(xd, lds, a.uni, fwd_tw, t);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      atomicAdd(&sums[0][r * TP + t], mulmod(xd[r], kv[r][0]));
+      atomicAdd(&sums[1][r * TP + t], mulmod(xd[r], kv[r][1]));
+    }
+    __syncthreads();  // every row's products are in; every rotation has read ACC
+    if (grp < 2) {
+      double y[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        y[r] = sums[grp][r * TP + t];
+        sums[grp][r * TP + t] = 0.0;  // cleared for the next step
+      }
+      ntt_inv_reg<LOGN>(y, lds, a.uni, inv_tw, post, t);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[grp][t + TP * r] += low32_magic(y[r]);
+    }
+    __syncthreads();  // ACC updated and the sums cleared before the next step
+  }
+
+#pragma unroll
+  for (uint32_t k = 0; k < 2; ++k) {
+    if (k > even) break;
+    const uint32_t fn = even ? k : lut;
+    uint32_t* out;
+    uint32_t plain = 0u;
+    if (a.out0) {
+      out = (fn == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
+      plain = a.plain_b[fn];
+    } else {
+      out = a.ext + (even ? 2 * job + k : job) * (size_t)(N + 1);
+    }
+    out = uniform_ptr(out);
+    for (int j = tid; j < N; j += NT) out[j] = j <= (int)k ? acc[0][k - j] : 0u - acc[0][N + k - j];
+    if (tid == 0) out[N] = acc[1][k] + plain;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Key switching z -> s with the bootstrapping epilogue.  Thread w owns
 // output word w of one sample.  out = (0, b') - sum over coefficients i and
 // digits j of KSK[i][j][d_ij - 1] (d_ij != 0), where a'_i is rounded to
@@ -596,11 +740,14 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // N = 1024 and (0, 1) at N = 2048.
 int blind_rotate_variants(uint32_t N) { return N == 1024 || N == 2048 ? 4 : 0; }
 
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, bool split,
+int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, int groups,
                         hipStream_t st) {
   if (jobs == 0) return 0;
   const dim3 g((uint32_t)jobs);
-  if (N == 1024) {
+  const bool split = groups == kBrTwo || (groups == kBrRows && N != 1024);
+  if (N == 1024 && groups == kBrRows) {
+    blind_rotate_rows_kernel<10, 3, 7><<<g, 6 * 64, 0, st>>>(a);
+  } else if (N == 1024) {
     if (split) {
       blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);
     } else {

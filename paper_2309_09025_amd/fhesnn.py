@@ -69,6 +69,7 @@ SIGNATURES = {
     "fs_decrypt": (_int, [_vp, _u32p, _sz, _u32, _i32p]),
     "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
     "fs_ctx_set_split": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "fs_ctx_set_rows": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "fs_evk_export": (_int, [_vp, _u32p, _u32p]),
     "fs_evk_params": (_int, [_vp, _PP]),
     "fs_secret_free": (None, [_vp]),
@@ -304,6 +305,30 @@ class Context:
         prev = ctypes.c_size_t()
         _check("fs_ctx_set_split", lib().fs_ctx_set_split(self.h, max_jobs, ctypes.byref(prev)))
         return prev.value
+
+    def set_rows(self, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs use one thread group per digit
+        row (lowest latency); returns the previous threshold."""
+        prev = ctypes.c_size_t()
+        _check("fs_ctx_set_rows", lib().fs_ctx_set_rows(self.h, max_jobs, ctypes.byref(prev)))
+        return prev.value
+
+    def groups(self, mode: str):
+        """Context manager forcing the thread groups per job: "one", "two"
+        or "rows" (restores the thresholds on exit)."""
+        import contextlib
+
+        @contextlib.contextmanager
+        def cm():
+            big = 1 << 40
+            rows, split = {"one": (0, 0), "two": (0, big), "rows": (big, 0)}[mode]
+            pr, ps = self.set_rows(rows), self.set_split(split)
+            try:
+                yield self
+            finally:
+                self.set_rows(pr)
+                self.set_split(ps)
+        return cm()
 
     def set_br_variant(self, N: int, variant: int):
         _check("fs_ctx_set_br_variant", lib().fs_ctx_set_br_variant(self.h, N, variant))

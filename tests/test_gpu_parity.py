@@ -71,13 +71,12 @@ def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     f = O.lut_reset(P.p, 4, 2)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
     ctx.set_br_variant(P.N, variant)
-    split = ctx.set_split(0)  # the one-group kernel of this variant
     try:
-        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
-        got = _host(out)
+        with ctx.groups("one"):  # the one-group kernel of this variant
+            F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
+            got = _host(out)
     finally:
         ctx.set_br_variant(P.N, 0)
-        ctx.set_split(split)
     assert np.array_equal(got, O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
 
 
@@ -90,21 +89,20 @@ def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, varian
     f = O.lut_fire(P.p, 4)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
     ctx.set_br_variant(P.N, variant)
-    split = ctx.set_split(0)  # the one-group kernel of this variant
     try:
-        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
-        got = _host(out)
+        with ctx.groups("one"):  # the one-group kernel of this variant
+            F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
+            got = _host(out)
     finally:
         ctx.set_br_variant(P.N, 0)
-        ctx.set_split(split)
     assert np.array_equal(got, O.pbs(okeys_b, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
 
 
 @pytest.mark.parametrize("shape,count,keyswitch", [(0, 5, True), (0, 70, True), (0, 9, False),
-                                                     (1, 3, True), (1, 66, True)])
+                                                     (0, 1, True), (1, 3, True), (1, 66, True)])
 def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, keyswitch):
-    """Two thread groups per job (small batches) and one group per job give
-    the oracle's bits, with and without the key switch."""
+    """One thread group per digit row (N = 1024), two per job and one per
+    job give the oracle's bits, with and without the key switch."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(shape)
     ok = okeys_a if shape == 0 else okeys_b
@@ -112,15 +110,11 @@ def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count,
     f = O.lut_reset(P.p, 4, 2)
     width = P.n + 1 if keyswitch else P.N + 1
     want = O.pbs(ok, O.test_poly(P.N, P.p, f), ct, keyswitch=keyswitch)
-    prev = ctx.set_split(1 << 20)
-    try:
-        for split in (1 << 20, 0):
-            ctx.set_split(split)
+    for mode in ("rows", "two", "one"):
+        with ctx.groups(mode):
             out = torch.zeros((count, width), dtype=torch.int32, device="cuda")
             F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=keyswitch)
-            assert np.array_equal(_host(out), want), split
-    finally:
-        ctx.set_split(prev)
+            assert np.array_equal(_host(out), want), mode
 
 
 @pytest.mark.parametrize("p_in,p_out,keyswitch", [(16, 32, True), (32, 8, True), (32, 8, False),
@@ -178,9 +172,10 @@ def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
     assert np.array_equal(_host(vv), vnew)
 
 
-@pytest.mark.parametrize("shape,count,split", [(0, 1, True), (0, 37, True), (0, 37, False),
-                                               (0, 600, False), (1, 3, True), (1, 5, False)])
-def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, split):
+@pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
+                                              (0, 21, "rows"), (0, 600, "one"), (1, 3, "two"),
+                                              (1, 5, "one")])
+def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Key switch of LWE_z(H), then Fire and Reset rotations extracted
     straight into the two outputs under z (one- and two-group kernels,
     ragged batch sizes): the oracle recomputes sampled neurons; at N = 1024
@@ -192,11 +187,8 @@ def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, co
     h = F.encrypt_z(sk, m, synth.SEED_ENC, 60000 + 1000 * shape + count)
     s2 = torch.zeros((count, P.N + 1), dtype=torch.int32, device="cuda")
     vv = torch.zeros_like(s2)
-    prev = ctx.set_split(1 << 20 if split else 0)
-    try:
+    with ctx.groups(mode):
         F.pbs_lif_ks_first(ctx, dk, 4, 2, _dev(h), s2, vv)
-    finally:
-        ctx.set_split(prev)
     got_s, got_v = _host(s2), _host(vv)
     idx = sorted({0, count // 2, count - 1})
     spikes, vnew = O.lif_step_ks_first(ok, 4, 2, h[idx])
@@ -210,9 +202,10 @@ def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, co
         assert wrong <= 1, wrong
 
 
-@pytest.mark.parametrize("shape,count,split", [(0, 1, True), (0, 37, True), (0, 37, False),
-                                               (0, 1100, False), (1, 3, True), (1, 5, False)])
-def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, split):
+@pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
+                                              (0, 13, "rows"), (0, 1100, "one"), (1, 3, "two"),
+                                              (1, 5, "one")])
+def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Fire and Reset from one even-exponent rotation per neuron (one- and
     two-group kernels, ragged batches, both shapes): sampled neurons equal
     the oracle's."""
@@ -223,11 +216,8 @@ def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, spl
     h = F.encrypt(sk, m, synth.SEED_ENC, 64000 + 1000 * shape + count)
     s2 = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
     vv = torch.zeros_like(s2)
-    prev = ctx.set_split(1 << 20 if split else 0)
-    try:
+    with ctx.groups(mode):
         F.pbs_lif_many_lut(ctx, dk, 4, 2, _dev(h), s2, vv)
-    finally:
-        ctx.set_split(prev)
     idx = sorted({0, count // 2, count - 1})
     spikes, vnew = O.lif_step_one_rotation(ok, 4, 2, h[idx])
     assert np.array_equal(_host(s2)[idx], spikes)

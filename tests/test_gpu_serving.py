@@ -24,21 +24,18 @@ def clients(gpu_env):
     return out
 
 
-@pytest.mark.parametrize("variant,split", [(0, None), (1, 0), (2, 0)])
-def test_pbs_lif_ranges_equals_one_call_per_range(gpu_env, clients, okeys_a, variant, split):
-    """Multi-key launch == one launch per range == oracle, on the two-group
-    kernel (small batch) and, with the split off, on two one-group
-    variants."""
+@pytest.mark.parametrize("variant,mode", [(0, "rows"), (0, "two"), (1, "one"), (2, "one")])
+def test_pbs_lif_ranges_equals_one_call_per_range(gpu_env, clients, okeys_a, variant, mode):
+    """Multi-key launch == one launch per range == oracle, on the row and
+    two-group kernels (small batches) and on two one-group variants."""
     ctx, _ = gpu_env
     P = F.params_default(0)
     ctx.set_br_variant(P.N, variant)
-    prev = ctx.set_split(split) if split is not None else None
     try:
-        _ranges_case(ctx, clients, okeys_a, P)
+        with ctx.groups(mode):
+            _ranges_case(ctx, clients, okeys_a, P)
     finally:
         ctx.set_br_variant(P.N, 0)
-        if prev is not None:
-            ctx.set_split(prev)
 
 
 def _ranges_case(ctx, clients, okeys_a, P):

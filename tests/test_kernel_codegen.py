@@ -63,8 +63,20 @@ def test_n1024_kernels_two_waves_no_scratch(compiled, args):
 
 def test_no_waterfall_loops_in_blind_rotation(compiled):
     usage, text = compiled
-    for name in (k for k in usage if "blind_rotate_kernel" in k):
+    for name in (k for k in usage if "blind_rotate" in k and "kernel" in k):
         body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
         # a waterfall loop compares a readfirstlane'd 64-bit value with the
         # vector register it came from
         assert "v_cmp_eq_u64" not in body, name
+
+
+def test_row_kernel_uses_lds_float_atomics(compiled):
+    """The row kernel sums the rows' products with hardware LDS binary64
+    atomic adds (a compare-and-swap loop would serialise them)."""
+    usage, text = compiled
+    name = "_ZN2fs24blind_rotate_rows_kernelILi10ELi3ELi7EEEvNS_6BrArgsE"
+    assert name in usage
+    assert usage[name].get("ScratchSize", 0) == 0
+    body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
+    assert "ds_add_f64" in body or "ds_add_rtn_f64" in body
+    assert "ds_cmpst" not in body and "ds_cmpswap" not in body
