@@ -198,10 +198,12 @@ FS_API int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous);
 
 /* Batches of at most max_jobs jobs (checked before the split threshold)
  * run each job on 2l groups, one per digit row of the external product
- * (Sec. 2.1, RGSW product; N = 1024): a CMux step's critical path is one
+ * (Sec. 2.1, RGSW product): a CMux step's critical path is one
  * forward and one inverse transform, for the lowest latency of a single
  * bootstrapping or a few.  Same results.  Default: 2 x the device's
- * compute units.  0 disables it.  *previous as above. */
+ * compute units.  0 disables it.  *previous as above.  Both thresholds
+ * are for N = 1024; at N = 2048 this one counts half and the split one a
+ * third (measured crossovers of the wider jobs). */
 FS_API int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous);
 
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of

@@ -241,10 +241,15 @@ int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const 
   return FS_OK;
 }
 
-// thread groups per job for a batch of this size (see launch_blind_rotate)
-int br_groups(const fs_ctx* ctx, size_t jobs) {
-  if (jobs <= ctx->rows_max_jobs) return kBrRows;
-  return jobs <= ctx->split_max_jobs ? kBrTwo : kBrOne;
+// thread groups per job for a batch of this size (see launch_blind_rotate).
+// The thresholds are set for N = 1024; at N = 2048 the row kernel holds one
+// job per CU (148 KiB of LDS) and the two-group kernel measured no faster
+// than one group beyond the row kernel's range, hence the scaling.
+int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs) {
+  const size_t rows = N == 2048 ? ctx->rows_max_jobs / 2 : ctx->rows_max_jobs;
+  const size_t split = N == 2048 ? ctx->split_max_jobs / 3 : ctx->split_max_jobs;
+  if (jobs <= rows) return kBrRows;
+  return jobs <= split ? kBrTwo : kBrOne;
 }
 
 // blind rotation of jobs = B * nlut, then key switch (or not)
@@ -273,7 +278,7 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   } else {
     br.ext = out0;
   }
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
                      "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
@@ -710,7 +715,7 @@ int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.post = dk->post;
   br.uni = dk->uni;
   br.ext = ctx->ext;
-  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, br_groups(ctx, B), st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, br_groups(ctx, P.N, B), st),
                  "blind rotation");
   if (rc) return rc;
   KsArgs ks{};
@@ -785,7 +790,7 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.plain_b[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
   br.plain_b[1] = 0u;
   return launch_rc(
-      launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
+      launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
       "blind rotation");
 }
 
@@ -862,7 +867,7 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   br.ext = ctx->ext;
   br.ranges = ctx->ranges;
   br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, jobs), st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
                  "blind rotation");
   if (rc) return rc;
   // one batched key switch per key over its adjacent ranges

@@ -310,25 +310,31 @@ blind_rotate_kernel(BrArgs a) {
 // Blind rotation for latency (small batches): one thread group of TP threads
 // per digit row, 2l groups per job.  Group g = c l + lv rotates ACC_c,
 // extracts digit level lv, transforms it and multiplies it with its key row
-// for both outputs; the products of all rows are summed in LDS with exact
-// binary64 atomic adds (integers below 4.9 P < 2^53, so the order of the
-// additions cannot change the sum).  Groups 0 and 1 then inverse-transform
-// output 0 and 1 and update ACC.  A step's critical path is one forward and
-// one inverse transform instead of three forward and one inverse (two-group
-// form) or six and two (one group).  Same bits as blind_rotate_kernel.
-template <int LOGN, int L, int BG>
+// for both outputs (and both key limbs at N = 2048); the products of all
+// rows are summed in LDS with exact binary64 atomic adds (integers below
+// 5 P < 2^53, so the order of the additions cannot change the sum).  Then
+// 2 x limbs groups inverse-transform one (output, limb) sum each and add
+// its low 32 bits (shifted by 16 per limb) into ACC with 32-bit atomics
+// (wrapping mod 2^32, again order-free).  A step's critical path is one
+// forward and one inverse transform.  Same bits as blind_rotate_kernel.
+template <int LOGN, int L, int BG, int LIMBS>
 __global__ void __launch_bounds__(2 * L * NttShape<LOGN>::TP)
 blind_rotate_rows_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
   constexpr int N = S::N, TP = S::TP, ROWS = 2 * L, NT = ROWS * TP;
+  constexpr int NINV = 2 * LIMBS;  // inverse transforms per step
   constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr uint32_t NU = LOGN + 1;
-  constexpr int G = 2;  // one key limb: mask and body values per slot
-  static_assert(TP == 64, "one wavefront per row");
+  constexpr int G = 2 * LIMBS;  // key values per slot: outputs x limbs
+  constexpr bool TAB1 = 2 * HALF <= 256;
+  static_assert(NINV <= ROWS, "an inverse transform per (output, limb) group");
+  // groups of several wavefronts synchronise their exchanges with workgroup
+  // barriers, so then every group must run the same transforms
+  static_assert(TP == 64 || NINV == ROWS, "uniform barrier sequence");
   __shared__ double lds_all[ROWS][S::LDS_DOUBLES];
-  __shared__ double sums[2][16 * TP];  // [output][r][t]: row products summed
+  __shared__ double sums[2][LIMBS][16 * TP];  // [output][limb][r][t]
   __shared__ uint32_t acc[2][N];
-  __shared__ double stage1[2 * HALF];
+  __shared__ double stage1[TAB1 ? 2 * HALF : 1];
 
   const int grp = (int)threadIdx.x / TP;
   const int t = (int)threadIdx.x - grp * TP;
@@ -361,9 +367,10 @@ blind_rotate_rows_kernel(BrArgs a) {
   auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
 
   const int tid = threadIdx.x;
-  for (int f = tid; f < (int)(2 * HALF); f += NT)
-    stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
-  for (int j = tid; j < 2 * 16 * TP; j += NT) (&sums[0][0])[j] = 0.0;
+  if constexpr (TAB1)
+    for (int f = tid; f < (int)(2 * HALF); f += NT)
+      stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
+  for (int j = tid; j < 2 * LIMBS * 16 * TP; j += NT) (&sums[0][0][0])[j] = 0.0;
   {
     const uint32_t bbar = mod_switch(ct[n]);
     const uint32_t e = (2 * N - bbar) & (2 * N - 1);
@@ -380,16 +387,25 @@ blind_rotate_rows_kernel(BrArgs a) {
   __syncthreads();
 
   const uint32_t sh = 32 - (lv + 1) * BG;
+  // key slice of this group's row: registers [r0, r0 + RN) of the 16
+  double kv[16][G];
+  auto load_key = [&](uint32_t row, int r0, int rn) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = r0; r < r0 + rn; ++r)
+#pragma unroll
+      for (int q = 0; q < G; q += 2)
+        key.at2((uint32_t)t * (G * 8), row + (uint32_t)((r * TP * G + q) * 8), kv[r][q],
+                kv[r][q + 1]);
+  };
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t abar = mod_switch(ct[i]);
     if (abar == 0) continue;
-    // this group's key row, requested before the transform
     const uint32_t row = i * (uint32_t)(ROWS * 16 * TP * G * 8) +
                          (uint32_t)(grp * 16 * TP * G * 8);
-    double kv[16][G];
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      key.at2((uint32_t)t * (G * 8), row + (uint32_t)(r * TP * G * 8), kv[r][0], kv[r][1]);
+    // the key row is requested before the transform (half of it when it is
+    // two limbs wide, to bound the registers held across the transform)
+    constexpr int PRE = G == 2 ? 16 : 8;
+    load_key(row, 0, PRE);
     // digit level lv of D_c = X^{a~} ACC_c - ACC_c (plus the rounding offset)
     double xd[16];
     {
@@ -403,31 +419,44 @@ blind_rotate_rows_kernel(BrArgs a) {
         const uint32_t neg = 0u - (((uint32_t)k >> LOGN) & 1u);
         d[r] = ((val ^ neg) - neg) - ac[t + TP * r] + off;
       }
+      if constexpr (TAB1) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const double x0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
-        const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
-        xd[r + 8] = x0 - m;
-        xd[r] = x0 + m;
+        for (int r = 0; r < 8; ++r) {
+          const double x0 =
+              (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+          const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
+          xd[r + 8] = x0 - m;
+          xd[r] = x0 + m;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
       }
     }
-    ntt_fwd_reg<LOGN, true>(xd, lds, a.uni, fwd_tw, t);
+    ntt_fwd_reg<LOGN, TAB1>(xd, lds, a.uni, fwd_tw, t);
+    if constexpr (PRE < 16) load_key(row, PRE, 16 - PRE);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      atomicAdd(&sums[0][r * TP + t], mulmod(xd[r], kv[r][0]));
-      atomicAdd(&sums[1][r * TP + t], mulmod(xd[r], kv[r][1]));
-    }
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int q = 0; q < G; ++q)  // q = output * LIMBS + limb
+        atomicAdd(&sums[q / LIMBS][q % LIMBS][r * TP + t], mulmod(xd[r], kv[r][q]));
     __syncthreads();  // every row's products are in; every rotation has read ACC
-    if (grp < 2) {
+    if (grp < NINV) {
+      const int co = grp / LIMBS, lb = grp % LIMBS;
       double y[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        y[r] = sums[grp][r * TP + t];
-        sums[grp][r * TP + t] = 0.0;  // cleared for the next step
+        y[r] = sums[co][lb][r * TP + t];
+        sums[co][lb][r * TP + t] = 0.0;  // cleared for the next step
       }
       ntt_inv_reg<LOGN>(y, lds, a.uni, inv_tw, post, t);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[grp][t + TP * r] += low32_magic(y[r]);
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t part = low32_magic(y[r]) << (16 * lb);
+        if constexpr (LIMBS == 1) acc[co][t + TP * r] += part;
+        else atomicAdd(&acc[co][t + TP * r], part);
+      }
     }
     __syncthreads();  // ACC updated and the sums cleared before the next step
   }
@@ -744,9 +773,11 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, i
                         hipStream_t st) {
   if (jobs == 0) return 0;
   const dim3 g((uint32_t)jobs);
-  const bool split = groups == kBrTwo || (groups == kBrRows && N != 1024);
-  if (N == 1024 && groups == kBrRows) {
-    blind_rotate_rows_kernel<10, 3, 7><<<g, 6 * 64, 0, st>>>(a);
+  const bool split = groups == kBrTwo;
+  if (groups == kBrRows) {
+    if (N == 1024) blind_rotate_rows_kernel<10, 3, 7, 1><<<g, 6 * 64, 0, st>>>(a);
+    else if (N == 2048) blind_rotate_rows_kernel<11, 2, 10, 2><<<g, 4 * 128, 0, st>>>(a);
+    else return -1;
   } else if (N == 1024) {
     if (split) {
       blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);

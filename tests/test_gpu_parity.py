@@ -174,7 +174,7 @@ def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
 
 @pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
                                               (0, 21, "rows"), (0, 600, "one"), (1, 3, "two"),
-                                              (1, 5, "one")])
+                                              (1, 5, "one"), (1, 4, "rows")])
 def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Key switch of LWE_z(H), then Fire and Reset rotations extracted
     straight into the two outputs under z (one- and two-group kernels,
@@ -204,7 +204,7 @@ def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, co
 
 @pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
                                               (0, 13, "rows"), (0, 1100, "one"), (1, 3, "two"),
-                                              (1, 5, "one")])
+                                              (1, 5, "one"), (1, 4, "rows")])
 def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Fire and Reset from one even-exponent rotation per neuron (one- and
     two-group kernels, ragged batches, both shapes): sampled neurons equal

@@ -70,12 +70,13 @@ def test_no_waterfall_loops_in_blind_rotation(compiled):
         assert "v_cmp_eq_u64" not in body, name
 
 
-def test_row_kernel_uses_lds_float_atomics(compiled):
+@pytest.mark.parametrize("args", [(10, 3, 7, 1), (11, 2, 10, 2)])
+def test_row_kernel_uses_lds_float_atomics(compiled, args):
     """The row kernel sums the rows' products with hardware LDS binary64
     atomic adds (a compare-and-swap loop would serialise them)."""
     usage, text = compiled
-    name = "_ZN2fs24blind_rotate_rows_kernelILi10ELi3ELi7EEEvNS_6BrArgsE"
-    assert name in usage
+    name = "_ZN2fs24blind_rotate_rows_kernelI" + "".join(f"Li{a}E" for a in args) + "EEvNS_6BrArgsE"
+    assert name in usage, sorted(k for k in usage if "rows" in k)
     assert usage[name].get("ScratchSize", 0) == 0
     body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
     assert "ds_add_f64" in body or "ds_add_rtn_f64" in body
