@@ -62,6 +62,34 @@ def test_pbs_fire_bit_exact(gpu_env, okeys_a, keyswitch):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("shape", [0, 1])
+def test_full_batch_in_the_benchmarked_configuration_sampled(gpu_env, okeys_a, okeys_b, shape):
+    """The benchmarked workload at its full size: 4096 fresh encryptions of
+    uniform messages through the LIF threshold function in one launch, with
+    the kernel variant the tuner picked for this batch and the matrix-core
+    key switch; the oracle recomputes sampled rows (first, last, the two
+    halves' boundary and random ones)."""
+    from paper_2309_09025_amd import tune
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(shape)
+    ok = okeys_a if shape == 0 else okeys_b
+    B = 4096
+    m = synth.messages(synth.SEED_DATA, B, P.p)
+    ct = F.encrypt(sk, m, synth.SEED_ENC)
+    fire, _ = F.lif_luts(4, 2, P.p)
+    variant, _ = tune.tune_blind_rotation(ctx, dk, B, use_cache=True)
+    out = torch.zeros((B, P.n + 1), dtype=torch.int32, device="cuda")
+    try:
+        F.pbs(ctx, dk, fire, _dev(ct), out, keyswitch=True)
+        got = _host(out)
+    finally:
+        ctx.set_br_variant(P.N, 0)
+    g = synth.rng(synth.SEED_DATA, 880 + shape)
+    idx = sorted({0, 1, B // 2 - 1, B // 2, B - 1, *g.integers(0, B, size=4 if shape == 0 else 1)})
+    want = O.pbs(ok, O.test_poly(P.N, P.p, fire), ct[idx], keyswitch=True)
+    assert np.array_equal(got[idx], want), variant
+
+
 @pytest.mark.parametrize("variant", range(4))
 def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     ctx, get = gpu_env
