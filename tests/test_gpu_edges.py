@@ -136,3 +136,33 @@ def test_empty_ranges_between_ranges(gpu_env, okeys_a):
     got_s = np.concatenate([F.to_host(s) for s, _ in outs])
     got_v = np.concatenate([F.to_host(v) for _, v in outs])
     assert np.array_equal(got_s, F.to_host(s_all)) and np.array_equal(got_v, F.to_host(v_all))
+
+
+def test_oversized_batches_are_rejected_before_any_work(gpu_env):
+    """Batch sizes past what a launch grid can address are refused with
+    FS_EINVAL by the C entry points themselves (the pointers are never
+    touched: they are placeholders here)."""
+    import ctypes
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    L = F.lib()
+    fake = ctypes.c_void_p(0x1000)
+    lut = np.zeros(P.p, np.int32)
+    lif = F.CLif(4, 2)
+    huge = 1 << 40
+    cases = {
+        "fs_pbs": lambda: L.fs_pbs(ctx.h, dk.h, lut.ctypes.data_as(F._i32p), fake, huge, fake, 1,
+                                   None),
+        "fs_pbs_lif": lambda: L.fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), fake, huge, fake,
+                                           ctypes.c_void_p(0x2000), None),
+        "fs_pbs_lif_ks_first": lambda: L.fs_pbs_lif_ks_first(ctx.h, dk.h, ctypes.byref(lif), fake,
+                                                             huge, fake, ctypes.c_void_p(0x2000),
+                                                             None),
+        "fs_pbs_lif_many_lut": lambda: L.fs_pbs_lif_many_lut(ctx.h, dk.h, ctypes.byref(lif), fake,
+                                                             huge, fake, ctypes.c_void_p(0x2000),
+                                                             None),
+        "fs_keyswitch": lambda: L.fs_keyswitch(ctx.h, dk.h, fake, huge, fake, None),
+    }
+    for name, call in cases.items():
+        assert call() == F.FS_EINVAL, name
+        assert "too large" in L.fs_last_error().decode(), name
