@@ -127,3 +127,14 @@ def test_header_is_plain_c99():
                         os.path.join(root, "tests", "c_header_only.c")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No fallback: with the shared library absent, the first call raises
+    instead of computing anything on the host."""
+    monkeypatch.setattr(F, "_lib", None)
+    monkeypatch.setattr(F, "LIB_PATH", "/nonexistent/libfhesnn.so")
+    with pytest.raises(ImportError):
+        F.params_default(0)
+    with pytest.raises(ImportError):
+        F.lif_luts(4, 2, 32)
