@@ -323,9 +323,20 @@ def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):
     batch.run(cts, [int(t) for t in Ts], [int(h) for h in Hs])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same batch with Fire and Reset read from one blind rotation per
+    # neuron (opt-in: doubled modulus-switching error, different ciphertexts)
+    one = NW.UnevenBatch(ctx, dk, Wc, nets, geom, NW.LifSpec(base.vth, base.tau), many_lut=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    one.run(cts, [int(t) for t in Ts], [int(h) for h in Hs])
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
     return {"workload": f"{images} synthetic images, T uniform in 2..8, hidden 256 or 800",
             "images": images, "predictions_per_s": round(images / dt, 3), "seconds": round(dt, 3),
-            "bootstrappings": batch.pbs_count, "pbs_per_s": round(batch.pbs_count / dt, 1)}
+            "bootstrappings": batch.pbs_count, "pbs_per_s": round(batch.pbs_count / dt, 1),
+            "one_rotation_per_neuron": {"predictions_per_s": round(images / dt1, 3),
+                                        "seconds": round(dt1, 3),
+                                        "blind_rotations": one.pbs_count // 2}}
 
 
 def _server(F, SV, synth, ctx, P, clients):

@@ -516,10 +516,13 @@ def lif_layer_run(keys: Keys, I_ct, vth: int, tau: int, T: int, nthreads=None,
     return Hs, Ss, Vs
 
 
-def conv_snn_run(keys: Keys, px_ct, Wc, W1, W2, geom, vth: int, tau: int, T: int, nthreads=None):
+def conv_snn_run(keys: Keys, px_ct, Wc, W1, W2, geom, vth: int, tau: int, T: int, nthreads=None,
+                 one_rotation: bool = False):
     """Conv layer (LIF) -> FC (LIF) -> FC accumulators, T steps; the conv
     current is computed once since the encrypted image is static.
-    geom = (Ci, H, Wd, stride, pad).  Returns per-step dicts of ciphertexts."""
+    geom = (Ci, H, Wd, stride, pad).  Returns per-step dicts of ciphertexts.
+    one_rotation: each LIF step uses lif_step_one_rotation."""
+    lif_step_ = lif_step_one_rotation if one_rotation else lif_step
     Ci, H, Wd, st, pd = geom
     I1 = lwe_conv2d(Wc, px_ct, Ci, H, Wd, st, pd)
     V1 = zero_ct(*I1.shape)
@@ -528,9 +531,9 @@ def conv_snn_run(keys: Keys, px_ct, Wc, W1, W2, geom, vth: int, tau: int, T: int
     steps = []
     for _ in range(T):
         H1 = (V1 + I1).astype(np.uint32)
-        S1, V1 = lif_step(keys, vth, tau, H1, nthreads)
+        S1, V1 = lif_step_(keys, vth, tau, H1, nthreads)
         H2 = lwe_linear(W1, S1, add=V2)
-        S2, V2 = lif_step(keys, vth, tau, H2, nthreads)
+        S2, V2 = lif_step_(keys, vth, tau, H2, nthreads)
         score = lwe_linear(W2, S2, add=score)
         steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, score=score.copy()))
     return I1, steps

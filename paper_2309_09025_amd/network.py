@@ -113,10 +113,15 @@ class LifLayerNet:
 
 
 class ConvSNN:
-    """conv (LIF) -> FC (LIF) -> FC score accumulators on one encrypted image."""
+    """conv (LIF) -> FC (LIF) -> FC score accumulators on one encrypted image.
+    many_lut: Fire and Reset from one blind rotation per neuron
+    (fs_pbs_lif_many_lut; per-step schedule only)."""
 
-    def __init__(self, ctx, dk, Wc, W1, W2, geom, lif: LifSpec = LifSpec(), capture: bool = False):
+    def __init__(self, ctx, dk, Wc, W1, W2, geom, lif: LifSpec = LifSpec(), capture: bool = False,
+                 many_lut: bool = False):
         self.ctx, self.dk, self.lif = ctx, dk, lif
+        self.act = F.pbs_lif_many_lut if many_lut else F.pbs_lif
+        self.many_lut = many_lut
         P = dk.params
         self.width = P.n + 1
         self.Ci, self.H, self.Wd, self.stride, self.pad = geom
@@ -141,9 +146,9 @@ class ConvSNN:
     def _step(self):
         c, dk, L = self.ctx, self.dk, self.lif
         F.lwe_add(c, self.V1, self.I1, self.H1)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        self.act(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
         F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        self.act(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
         F.lwe_linear(c, self.W2, self.S2, self.score, add=self.score)
 
     def run(self, px_ct: torch.Tensor, T: int, record: bool = False):
@@ -172,6 +177,8 @@ class ConvSNN:
         it is bootstrapped in the same launch (fs_pbs_lif_ranges) as layer 2
         at step t.  T + 1 launches instead of 2T, fewer partly filled rounds
         for one image; the results are bit-identical to run()."""
+        if self.many_lut:
+            raise NotImplementedError("the pipelined schedule runs the two-rotation activation")
         c, dk, L = self.ctx, self.dk, self.lif
         F.lwe_conv2d(c, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd, self.stride,
                      self.pad)
@@ -469,9 +476,11 @@ class UnevenBatch:
     replayed for as many steps as it lasts."""
 
     def __init__(self, ctx, dk, Wc, nets: dict, geom, lif: LifSpec = LifSpec(),
-                 capture: bool = True):
-        """nets: hidden width -> (W1 [H][l1], W2 [classes][H])."""
+                 capture: bool = True, many_lut: bool = False):
+        """nets: hidden width -> (W1 [H][l1], W2 [classes][H]); many_lut: Fire
+        and Reset from one blind rotation per neuron."""
         self.ctx, self.dk, self.lif = ctx, dk, lif
+        self.act = F.pbs_lif_many_lut if many_lut else F.pbs_lif
         P = dk.params
         self.width = P.n + 1
         self.Ci, self.Hh, self.Wd, self.stride, self.pad = geom
@@ -511,12 +520,12 @@ class UnevenBatch:
 
             def step():
                 F.lwe_add(ctx, V1[:n1], I1[:n1], H1[:n1])
-                F.pbs_lif(ctx, self.dk, L.v_th, L.tau, H1[:n1], S1[:n1], V1[:n1])
+                self.act(ctx, self.dk, L.v_th, L.tau, H1[:n1], S1[:n1], V1[:n1])
                 for k in range(active):
                     W1, W2 = self.nets[Hs_s[k]]
                     a, b = int(off2[k]), int(off2[k + 1])
                     F.lwe_linear(ctx, W1, S1[k * l1:(k + 1) * l1], H2[a:b], add=V2[a:b])
-                F.pbs_lif(ctx, self.dk, L.v_th, L.tau, H2[:n2], S2[:n2], V2[:n2])
+                self.act(ctx, self.dk, L.v_th, L.tau, H2[:n2], S2[:n2], V2[:n2])
                 for k in range(active):
                     W1, W2 = self.nets[Hs_s[k]]
                     a, b = int(off2[k]), int(off2[k + 1])

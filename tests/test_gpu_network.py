@@ -97,6 +97,36 @@ def test_conv_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     assert np.array_equal(score, osteps[-1]["score"])
 
 
+def test_conv_snn_mini_many_lut_bit_exact_and_in_an_uneven_batch(gpu_env, okeys_a):
+    """The conv SNN with Fire and Reset from one rotation per neuron: equal to
+    the oracle's same form at every step, and the uneven batch of such
+    networks equals each image run alone."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.CONV_SNN_MINI
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), capture=True,
+                     many_lut=True)
+    x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
+    score, steps = net.run(x, cfg.T, record=True)
+    _, osteps = O.conv_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
+                               Wc, W1, W2, geom, cfg.vth, cfg.tau, cfg.T, one_rotation=True)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert np.array_equal(steps[t][k], osteps[t][k]), (t, k)
+    with pytest.raises(NotImplementedError):
+        net.run_pipelined(x, cfg.T)
+    cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 3000 * k))
+           for k in range(3)]
+    batch = NW.UnevenBatch(ctx, dk, Wc, {cfg.hidden: (W1, W2)}, geom,
+                           NW.LifSpec(cfg.vth, cfg.tau), many_lut=True)
+    got = batch.run(cts, [2, 3, 1], [cfg.hidden] * 3)
+    for k, T in enumerate([2, 3, 1]):
+        alone, _ = net.run(cts[k], T)
+        assert np.array_equal(got[k], alone), k
+
+
 def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
     """Config 3 at full size (28x28 image, conv 1->8 5x5 s2 p2, FC 1568->256,
     FC 256->10, T = 4), graph-replayed.  The oracle recomputes the conv
