@@ -213,9 +213,13 @@ def single_image(F, NW, synth, ctx, dk, sk, images=3):
     args_of = lambda k: (cts[k], cfg.T)
     m_steps = _image_latency(net.run, args_of, images)
     m_pipe = _image_latency(net.run_pipelined, args_of, images)
-    return _single_image_record(
+    rec = _single_image_record(
         "conv SNN, 1 synthetic 28x28 image, conv 1->8 5x5 s2 p2 (LIF) -> FC 1568->256 "
         "(LIF) -> FC 256->10 accumulators, T=4", cfg.pbs_count(), m_steps, m_pipe)
+    one = NW.ConvSNN(ctx, dk, Wc, W1, W2, geom, NW.LifSpec(cfg.vth, cfg.tau), many_lut=True)
+    m_one = _image_latency(one.run_pipelined, args_of, images)
+    rec["one_rotation_per_neuron_pipelined_ms"] = round(m_one * 1e3, 2)
+    return rec
 
 
 def tiny_lif(F, NW, synth, ctx, dk, sk, reps=5):
@@ -281,10 +285,15 @@ def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
     args_of = lambda k: (cts[k], cfg.T)
     m_steps = _image_latency(net.run, args_of, images)
     m_pipe = _image_latency(net.run_pipelined, args_of, images)
-    return _single_image_record(
+    rec = _single_image_record(
         "paper CSNN topology, 1 synthetic 28x28 image, conv 1->10 8x8 s2 p1 (LIF) "
         "-> 2x2 average pool folded into FC 360->160 (LIF) -> FC 160->10 (LIF), "
         "spike-count scores, T=4", cfg.pbs_count(), m_steps, m_pipe)
+    one = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau),
+                       many_lut=True)
+    m_one = _image_latency(one.run_pipelined, args_of, images)
+    rec["one_rotation_per_neuron_pipelined_ms"] = round(m_one * 1e3, 2)
+    return rec
 
 
 def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):

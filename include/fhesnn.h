@@ -317,6 +317,12 @@ typedef struct fs_lif_range {
 FS_API int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
                              size_t nranges, void* stream);
 
+/* fs_pbs_lif_ranges with the one-rotation activation of fs_pbs_lif_many_lut
+ * (Fire and Reset read from one even-exponent blind rotation per neuron;
+ * its doubled rounding error applies).  Same ranges, keys and outputs. */
+FS_API int fs_pbs_lif_ranges_many_lut(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
+                                      size_t nranges, void* stream);
+
 /* Key switching z -> s alone (Sec. 2.1, Key Switching step).
  * in: dev [B][N+1] under z; out: dev [B][n+1] under s. */
 FS_API int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,

@@ -555,11 +555,13 @@ def lwe_sum_pool(ct, C: int, H: int, W: int, k: int):
 
 
 def paper_csnn_run(keys: Keys, px_ct, Wc, W1, W2, geom, pool: int, vth: int, tau: int, T: int,
-                   nthreads=None):
+                   nthreads=None, one_rotation: bool = False):
     """The paper's CSNN (Sec. 3.1) on ciphertexts: conv (LIF) -> average pool
     (window sum, Sec. 3.3) -> FC (LIF) -> FC (LIF), scores = the encrypted
     spike counts of the output layer, sum_t LWE(2S[t]).  Two bootstrappings
-    per LIF neuron per step (Table 1).  geom = (Ci, H, Wd, stride, pad)."""
+    per LIF neuron per step (Table 1).  geom = (Ci, H, Wd, stride, pad).
+    one_rotation: each LIF step uses lif_step_one_rotation."""
+    lif_step_ = lif_step_one_rotation if one_rotation else lif_step
     Ci, H, Wd, st, pd = geom
     Co, _, K, _ = np.asarray(Wc).shape
     Ho = (H + 2 * pd - K) // st + 1
@@ -573,11 +575,11 @@ def paper_csnn_run(keys: Keys, px_ct, Wc, W1, W2, geom, pool: int, vth: int, tau
     steps = []
     for _ in range(T):
         H1 = (V1 + I1).astype(np.uint32)
-        S1, V1 = lif_step(keys, vth, tau, H1, nthreads)
+        S1, V1 = lif_step_(keys, vth, tau, H1, nthreads)
         H2 = lwe_linear(W1, lwe_sum_pool(S1, Co, Ho, Wo, pool), add=V2)
-        S2, V2 = lif_step(keys, vth, tau, H2, nthreads)
+        S2, V2 = lif_step_(keys, vth, tau, H2, nthreads)
         H3 = lwe_linear(W2, S2, add=V3)
-        S3, V3 = lif_step(keys, vth, tau, H3, nthreads)
+        S3, V3 = lif_step_(keys, vth, tau, H3, nthreads)
         score = (score.astype(np.uint64) + S3).astype(np.uint32)
         steps.append(dict(H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, H3=H3, S3=S3, V3=V3,
                           score=score.copy()))
@@ -606,10 +608,12 @@ def poisson_spikes(keys: Keys, px_ct, m_t):
 
 
 def poisson_snn_run(keys: Keys, px_ct, thresholds, W1, W2, vth: int, tau: int, T: int,
-                    nthreads=None):
+                    nthreads=None, one_rotation: bool = False):
     """The Poisson-encoded SNN (Sec. 5.1, Table 1): per step the pixel spikes
     of poisson_spikes, FC (LIF), FC (LIF), scores = the encrypted spike counts
-    of the output layer."""
+    of the output layer.  one_rotation: the LIF steps use
+    lif_step_one_rotation."""
+    lif_step_ = lif_step_one_rotation if one_rotation else lif_step
     w = np.asarray(px_ct).shape[1]
     V1 = zero_ct(W1.shape[0], w)
     V2 = zero_ct(W2.shape[0], w)
@@ -618,9 +622,9 @@ def poisson_snn_run(keys: Keys, px_ct, thresholds, W1, W2, vth: int, tau: int, T
     for t in range(T):
         S0 = poisson_spikes(keys, px_ct, thresholds[t])
         H1 = lwe_linear(W1, S0, add=V1)
-        S1, V1 = lif_step(keys, vth, tau, H1, nthreads)
+        S1, V1 = lif_step_(keys, vth, tau, H1, nthreads)
         H2 = lwe_linear(W2, S1, add=V2)
-        S2, V2 = lif_step(keys, vth, tau, H2, nthreads)
+        S2, V2 = lif_step_(keys, vth, tau, H2, nthreads)
         score = (score.astype(np.uint64) + S2).astype(np.uint32)
         steps.append(dict(S0=S0, H1=H1, S1=S1, V1=V1, H2=H2, S2=S2, V2=V2, score=score.copy()))
     return steps

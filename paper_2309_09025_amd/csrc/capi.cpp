@@ -794,8 +794,14 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
       "blind rotation");
 }
 
-int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
-                      size_t nranges, void* stream) {
+namespace fs {
+namespace {
+// fs_pbs_lif_ranges and its one-rotation form: the blind rotation writes two
+// extracted samples per neuron (rows 2 g and 2 g + 1: Fire, Reset) either
+// from two jobs per neuron or, `many`, from one even-exponent rotation of
+// the interleaved test polynomial; the key switches are the same.
+int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, size_t nranges,
+                   void* stream, bool many) {
   if (!ctx || !lif || (nranges && !ranges)) return fail(FS_EINVAL, "fs_pbs_lif_ranges: null argument");
   // order: ranges of one key adjacent (stable), empty ranges dropped
   std::vector<size_t> order;
@@ -818,6 +824,7 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   }
   if (P.ks_t != 8 || P.ks_base_bit != 2)
     return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: needs the t = 8, base 4 key switch");
+  if (many && P.p > P.N) return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: one rotation needs p <= N");
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
     return (uintptr_t)ranges[x].key < (uintptr_t)ranges[y].key;
   });
@@ -828,9 +835,13 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   uint32_t* tp[2] = {nullptr, nullptr};
-  rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
-  if (rc) return rc;
-  rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
+  if (many) {
+    rc = get_tpoly_two(ctx, P.N, P.p, fire.data(), reset.data(), &tp[0]);
+    tp[1] = tp[0];
+  } else {
+    rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
+    if (!rc) rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
+  }
   if (rc) return rc;
   auto& host = ctx->ranges_host;
   host.clear();
@@ -850,15 +861,16 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
   }
   FS_HIP(hipMemcpyAsync(ctx->ranges, host.data(), host.size() * sizeof(JobRange),
                         hipMemcpyHostToDevice, st));
-  const size_t jobs = 2 * total;
-  rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
+  const size_t jobs = many ? total : 2 * total;
+  rc = ensure_ext(ctx, 2 * total * (size_t)(P.N + 1));
   if (rc) return rc;
   auto vit = ctx->br_variant.find(P.N);
   const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
   BrArgs br{};
   br.tpoly0 = tp[0];
   br.tpoly1 = tp[1];
-  br.nlut = 2;
+  br.nlut = many ? 1 : 2;
+  br.even = many ? 1u : 0u;
   br.n = P.n;
   br.fwd_tw = ranges[order[0]].key->fwd_tw;  // tables depend on N only
   br.inv_tw = ranges[order[0]].key->inv_tw;
@@ -897,6 +909,18 @@ int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges
     a = b;
   }
   return FS_OK;
+}
+}  // namespace
+}  // namespace fs
+
+int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
+                      size_t nranges, void* stream) {
+  return pbs_lif_ranges(ctx, lif, ranges, nranges, stream, false);
+}
+
+int fs_pbs_lif_ranges_many_lut(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
+                               size_t nranges, void* stream) {
+  return pbs_lif_ranges(ctx, lif, ranges, nranges, stream, true);
 }
 
 int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,

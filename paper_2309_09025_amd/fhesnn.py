@@ -99,6 +99,7 @@ SIGNATURES = {
     "fs_pbs_lif_many_lut": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ks_first": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
+    "fs_pbs_lif_ranges_many_lut": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "fs_ntt_polymul": (_int, [_vp, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
 }
@@ -457,13 +458,21 @@ def pbs_lif_ks_first(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_ou
                                      _dptr(spike2_out), _dptr(v_out), _stream(stream)))
 
 
-def pbs_lif_ranges(ctx: Context, v_th: int, tau: int, ranges, stream=None):
-    """ranges: iterable of (DevKey, h, spike2_out, v_out) device tensors."""
-    rs = [CLifRange(dk.h, _dptr(h).value, _dptr(s2).value, _dptr(v).value, h.shape[0])
-          for dk, h, s2, v in ranges]
+def pbs_lif_ranges(ctx: Context, v_th: int, tau: int, ranges, stream=None,
+                   many_lut: bool = False):
+    """ranges: iterable of (DevKey, h, spike2_out, v_out) device tensors, each
+    [count][n+1]; many_lut: the one-rotation activation."""
+    rs = []
+    for dk, h, s2, v in ranges:
+        w = dk.params.n + 1
+        for t in (h, s2, v):
+            if t.dim() != 2 or t.shape[1] != w or t.shape[0] != h.shape[0]:
+                raise ValueError(f"pbs_lif_ranges: buffers of a range must be [{h.shape[0]}][{w}]")
+        rs.append(CLifRange(dk.h, _dptr(h).value, _dptr(s2).value, _dptr(v).value, h.shape[0]))
     arr = (CLifRange * max(1, len(rs)))(*rs)
-    _check("fs_pbs_lif_ranges", lib().fs_pbs_lif_ranges(ctx.h, ctypes.byref(CLif(v_th, tau)),
-                                                        arr, len(rs), _stream(stream)))
+    fn = "fs_pbs_lif_ranges_many_lut" if many_lut else "fs_pbs_lif_ranges"
+    _check(fn, getattr(lib(), fn)(ctx.h, ctypes.byref(CLif(v_th, tau)), arr, len(rs),
+                                  _stream(stream)))
 
 
 def keyswitch(ctx: Context, dk: DevKey, x, out, stream=None):

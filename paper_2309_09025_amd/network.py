@@ -16,7 +16,7 @@ kernel in the step is one of the library's.
 from __future__ import annotations
 
 import contextlib
-
+import gc
 from dataclasses import dataclass
 
 import numpy as np
@@ -37,7 +37,12 @@ class LifSpec:
 
 class StepGraph:
     """Runs `fn` eagerly once (so test polynomials and scratch are in place),
-    then captures it into a HIP graph; `replay()` replays it."""
+    then captures it into a HIP graph; `replay()` replays it.
+
+    The cyclic garbage collector is held off while a capture is open: a
+    network holding its own StepGraph (through the bound step method) is a
+    reference cycle, and destroying its graph from inside another capture is
+    an operation the runtime forbids during capture."""
 
     def __init__(self, fn, capture: bool):
         self.fn = fn
@@ -56,8 +61,14 @@ class StepGraph:
             self._pending = True
             return
         if self._pending:
-            with torch.cuda.graph(self.graph):
-                self.fn()
+            was_enabled = gc.isenabled()
+            gc.disable()
+            try:
+                with torch.cuda.graph(self.graph):
+                    self.fn()
+            finally:
+                if was_enabled:
+                    gc.enable()
             self._pending = False
         self.graph.replay()
 
@@ -115,7 +126,7 @@ class LifLayerNet:
 class ConvSNN:
     """conv (LIF) -> FC (LIF) -> FC score accumulators on one encrypted image.
     many_lut: Fire and Reset from one blind rotation per neuron
-    (fs_pbs_lif_many_lut; per-step schedule only)."""
+    (fs_pbs_lif_many_lut)."""
 
     def __init__(self, ctx, dk, Wc, W1, W2, geom, lif: LifSpec = LifSpec(), capture: bool = False,
                  many_lut: bool = False):
@@ -177,8 +188,6 @@ class ConvSNN:
         it is bootstrapped in the same launch (fs_pbs_lif_ranges) as layer 2
         at step t.  T + 1 launches instead of 2T, fewer partly filled rounds
         for one image; the results are bit-identical to run()."""
-        if self.many_lut:
-            raise NotImplementedError("the pipelined schedule runs the two-rotation activation")
         c, dk, L = self.ctx, self.dk, self.lif
         F.lwe_conv2d(c, self.Wc, px_ct, self.I1, self.Ci, self.H, self.Wd, self.stride,
                      self.pad)
@@ -193,7 +202,7 @@ class ConvSNN:
             if k < T:
                 F.lwe_add(c, self.V1, self.I1, self.H1)
                 jobs.append((dk, self.H1, self.S1, self.V1))
-            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, many_lut=self.many_lut)
             self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
             if k >= 1:
                 F.lwe_linear(c, self.W2, self.S2, self.score, add=self.score)
@@ -231,8 +240,10 @@ class PaperCSNN:
     ConvSNN's plus the output layer; each timestep is one HIP graph."""
 
     def __init__(self, ctx, dk, Wc, W1, W2, geom, pool: int = 2, lif: LifSpec = LifSpec(),
-                 capture: bool = True):
+                 capture: bool = True, many_lut: bool = False):
         self.ctx, self.dk, self.lif = ctx, dk, lif
+        self.many_lut = many_lut  # Fire and Reset from one blind rotation per neuron
+        self.act = F.pbs_lif_many_lut if many_lut else F.pbs_lif
         P = dk.params
         self.width = w = P.n + 1
         self.Ci, self.H, self.Wd, self.stride, self.pad = geom
@@ -256,11 +267,11 @@ class PaperCSNN:
     def _step(self):
         c, dk, L = self.ctx, self.dk, self.lif
         F.lwe_add(c, self.V1, self.I1, self.H1)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        self.act(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
         F.lwe_linear(c, self.W1, self.S1, self.H2, add=self.V2)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        self.act(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
         F.lwe_linear(c, self.W2, self.S2, self.H3, add=self.V3)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H3, self.S3, self.V3)
+        self.act(c, dk, L.v_th, L.tau, self.H3, self.S3, self.V3)
         F.lwe_add(c, self.score, self.S3, self.score)
 
     def run(self, px_ct, T: int, record: bool = False):
@@ -308,7 +319,7 @@ class PaperCSNN:
             if k < T:
                 F.lwe_add(c, self.V1, self.I1, self.H1)
                 jobs.append((dk, self.H1, self.S1, self.V1))
-            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs)
+            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, many_lut=self.many_lut)
             self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
             if 2 <= k:
                 F.lwe_add(c, self.score, self.S3, self.score)
@@ -334,8 +345,11 @@ class PoissonSNN:
     timestep is one HIP graph; the step's threshold row is copied into a
     fixed buffer before the replay."""
 
-    def __init__(self, ctx, dk, W1, W2, lif: LifSpec = LifSpec(), capture: bool = True):
+    def __init__(self, ctx, dk, W1, W2, lif: LifSpec = LifSpec(), capture: bool = True,
+                 many_lut: bool = False):
         self.ctx, self.dk, self.lif = ctx, dk, lif
+        self.many_lut = many_lut  # the LIF layers read Fire and Reset from one rotation
+        self.act = F.pbs_lif_many_lut if many_lut else F.pbs_lif
         P = dk.params
         self.p = P.p
         self.width = w = P.n + 1
@@ -362,9 +376,9 @@ class PoissonSNN:
         F.pbs(c, dk, self.fire1, self.H0, self.S0, keyswitch=True)
         F.lwe_add_plain(c, self.p, self.S0, self.ones, self.S0)
         F.lwe_linear(c, self.W1, self.S0, self.H1, add=self.V1)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
+        self.act(c, dk, L.v_th, L.tau, self.H1, self.S1, self.V1)
         F.lwe_linear(c, self.W2, self.S1, self.H2, add=self.V2)
-        F.pbs_lif(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
+        self.act(c, dk, L.v_th, L.tau, self.H2, self.S2, self.V2)
         F.lwe_add(c, self.score, self.S2, self.score)
 
     def run(self, px_ct, thresholds, record: bool = False):
@@ -440,7 +454,7 @@ class PoissonSNN:
                     coded = torch.cuda.Event()
                     coded.record(side)
             if jobs:
-                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, stream=main)
+                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, stream=main, many_lut=self.many_lut)
                 self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
             if 2 <= k:
                 F.lwe_add(c, self.score, self.S2, self.score)

@@ -115,8 +115,10 @@ def test_conv_snn_mini_many_lut_bit_exact_and_in_an_uneven_batch(gpu_env, okeys_
     for t in range(cfg.T):
         for k in ("H1", "S1", "V1", "H2", "S2", "V2", "score"):
             assert np.array_equal(steps[t][k], osteps[t][k]), (t, k)
-    with pytest.raises(NotImplementedError):
-        net.run_pipelined(x, cfg.T)
+    pscore, psteps = net.run_pipelined(x, cfg.T, record=True)  # one launch per wave
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert np.array_equal(psteps[t][k], osteps[t][k]), (t, k)
     cts = [F.to_device(F.encrypt(sk, cfg.data(image_stream=k)[0], synth.SEED_ENC, 3000 * k))
            for k in range(3)]
     batch = NW.UnevenBatch(ctx, dk, Wc, {cfg.hidden: (W1, W2)}, geom,
@@ -125,6 +127,38 @@ def test_conv_snn_mini_many_lut_bit_exact_and_in_an_uneven_batch(gpu_env, okeys_
     for k, T in enumerate([2, 3, 1]):
         alone, _ = net.run(cts[k], T)
         assert np.array_equal(got[k], alone), k
+
+
+def test_paper_and_poisson_mini_many_lut_pipelined_bit_exact(gpu_env, okeys_a):
+    """The paper's CSNN and the Poisson SNN with the one-rotation activation,
+    software-pipelined (multi-range launches in that form), against the
+    oracle's same form at every step."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    cfg = synth.PAPER_CSNN_MINI
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    net = NW.PaperCSNN(ctx, dk, Wc, W1, W2, geom, cfg.pool, NW.LifSpec(cfg.vth, cfg.tau),
+                       many_lut=True)
+    score, steps = net.run_pipelined(F.to_device(F.encrypt(sk, px, synth.SEED_ENC)), cfg.T,
+                                     record=True)
+    _, osteps = O.paper_csnn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC),
+                                 Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T,
+                                 one_rotation=True)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "H3", "S3", "V3", "score"):
+            assert np.array_equal(steps[t][k], osteps[t][k]), (t, k)
+    pc = synth.POISSON_SNN_MINI
+    ppx, PW1, PW2 = pc.data()
+    thr = pc.thresholds()
+    pnet = NW.PoissonSNN(ctx, dk, PW1, PW2, NW.LifSpec(pc.vth, pc.tau), many_lut=True)
+    pscore, psteps = pnet.run_pipelined(F.to_device(F.encrypt(sk, ppx, synth.SEED_ENC)), thr,
+                                        record=True, side_ctx=F.Context(0))
+    posteps = O.poisson_snn_run(okeys_a, O.encrypt(O.SHAPE_A, okeys_a.s, ppx, synth.SEED_ENC),
+                                thr, PW1, PW2, pc.vth, pc.tau, pc.T, one_rotation=True)
+    for t in range(pc.T):
+        for k in ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert np.array_equal(psteps[t][k], posteps[t][k]), (t, k)
 
 
 def test_conv_snn_full_size_sampled(gpu_env, okeys_a):

@@ -138,3 +138,51 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
         F.params_default(0)
     with pytest.raises(ImportError):
         F.lif_luts(4, 2, 32)
+
+
+def test_step_graph_holds_off_the_garbage_collector_while_capturing(monkeypatch):
+    """A dead network that still holds a captured graph must not be freed
+    inside another capture: the collector is off for exactly the capture."""
+    import gc
+    import torch
+    from paper_2309_09025_amd import network as NW
+
+    seen = []
+
+    class FakeGraph:
+        def replay(self):
+            seen.append(("replay", gc.isenabled()))
+
+    class FakeCapture:
+        def __init__(self, graph):
+            pass
+
+        def __enter__(self):
+            seen.append(("begin", gc.isenabled()))
+
+        def __exit__(self, *exc):
+            seen.append(("end", gc.isenabled()))
+            return False
+
+    monkeypatch.setattr(torch.cuda, "CUDAGraph", FakeGraph)
+    monkeypatch.setattr(torch.cuda, "graph", FakeCapture)
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda: None)
+    calls = []
+    g = NW.StepGraph(lambda: calls.append(gc.isenabled()), capture=True)
+    assert gc.isenabled()
+    for _ in range(3):
+        g.run()
+    assert calls == [True, False]  # eager step, then the step inside the capture
+    assert seen == [("begin", False), ("end", False), ("replay", True), ("replay", True)]
+    assert gc.isenabled()
+
+    def boom():
+        raise RuntimeError("step failed")
+
+    g2 = NW.StepGraph(boom, capture=True)
+    g2.fn = lambda: None
+    g2.run()
+    g2.fn = boom
+    with pytest.raises(RuntimeError):
+        g2.run()
+    assert gc.isenabled()  # restored after a failed capture too
