@@ -310,10 +310,14 @@ def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
     m_steps = _image_latency(net.run, args_of, images)
     side = F.Context(0)  # the pixel coding on a second stream, beside the LIF launch
     m_pipe = _image_latency(lambda x, t: net.run_pipelined(x, t, side_ctx=side), args_of, images)
-    return _single_image_record(
+    rec = _single_image_record(
         "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
         "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "
         "spike-count scores, T1=20", cfg.pbs_count(), m_steps, m_pipe)
+    one = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), many_lut=True)
+    m_one = _image_latency(lambda x, t: one.run_pipelined(x, t, side_ctx=side), args_of, images)
+    rec["one_rotation_per_neuron_pipelined_ms"] = round(m_one * 1e3, 2)
+    return rec
 
 
 def uneven_batch(F, NW, synth, ctx, dk, sk, images=64):

@@ -297,6 +297,121 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   return launch_rc(launch_keyswitch(ks, jobs, st), "key switch");
 }
 
+// fs_pbs_lif_ranges and its one-rotation form: the blind rotation writes two
+// extracted samples per neuron (rows 2 g and 2 g + 1: Fire, Reset) either
+// from two jobs per neuron or, `many`, from one even-exponent rotation of
+// the interleaved test polynomial; the key switches are the same.
+int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, size_t nranges,
+                   void* stream, bool many) {
+  if (!ctx || !lif || (nranges && !ranges)) return fail(FS_EINVAL, "fs_pbs_lif_ranges: null argument");
+  // order: ranges of one key adjacent (stable), empty ranges dropped
+  std::vector<size_t> order;
+  for (size_t k = 0; k < nranges; ++k) {
+    const fs_lif_range& r = ranges[k];
+    if (r.count == 0) continue;
+    if (!r.key || !r.h || !r.spike2_out || !r.v_out)
+      return fail(FS_EINVAL, "fs_pbs_lif_ranges: null pointer in a range");
+    order.push_back(k);
+  }
+  if (order.empty()) return FS_OK;
+  const fs_params& P = ranges[order[0]].key->prm;
+  for (size_t k : order) {
+    const fs_params& Q = ranges[k].key->prm;
+    if (Q.n != P.n || Q.N != P.N || Q.l != P.l || Q.bg_bit != P.bg_bit || Q.p != P.p ||
+        Q.ks_t != P.ks_t || Q.ks_base_bit != P.ks_base_bit)
+      return fail(FS_EPARAM, "fs_pbs_lif_ranges: keys of different parameter sets");
+    if (ranges[k].key->device != ctx->device)
+      return fail(FS_EPARAM, "fs_pbs_lif_ranges: a key lives on another device");
+  }
+  if (P.ks_t != 8 || P.ks_base_bit != 2)
+    return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: needs the t = 8, base 4 key switch");
+  if (many && P.p > P.N) return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: one rotation needs p <= N");
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    return (uintptr_t)ranges[x].key < (uintptr_t)ranges[y].key;
+  });
+  std::vector<int32_t> fire(P.p), reset(P.p);
+  int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  uint32_t* tp[2] = {nullptr, nullptr};
+  if (many) {
+    rc = get_tpoly_two(ctx, P.N, P.p, fire.data(), reset.data(), &tp[0]);
+    tp[1] = tp[0];
+  } else {
+    rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
+    if (!rc) rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
+  }
+  if (rc) return rc;
+  auto& host = ctx->ranges_host;
+  host.clear();
+  uint64_t total = 0;
+  for (size_t k : order) {
+    const fs_lif_range& r = ranges[k];
+    host.push_back(JobRange{r.h, r.spike2_out, r.v_out, r.key->bsk, total});
+    total += r.count;
+  }
+  if (total > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ranges: batch too large");
+  if (ctx->ranges_cap < host.size()) {
+    if (ctx->ranges) FS_HIP(hipFree(ctx->ranges));
+    ctx->ranges = nullptr;
+    ctx->ranges_cap = 0;
+    FS_HIP(hipMalloc(&ctx->ranges, host.size() * sizeof(JobRange)));
+    ctx->ranges_cap = host.size();
+  }
+  FS_HIP(hipMemcpyAsync(ctx->ranges, host.data(), host.size() * sizeof(JobRange),
+                        hipMemcpyHostToDevice, st));
+  const size_t jobs = many ? total : 2 * total;
+  rc = ensure_ext(ctx, 2 * total * (size_t)(P.N + 1));
+  if (rc) return rc;
+  auto vit = ctx->br_variant.find(P.N);
+  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
+  BrArgs br{};
+  br.tpoly0 = tp[0];
+  br.tpoly1 = tp[1];
+  br.nlut = many ? 1 : 2;
+  br.even = many ? 1u : 0u;
+  br.n = P.n;
+  br.fwd_tw = ranges[order[0]].key->fwd_tw;  // tables depend on N only
+  br.inv_tw = ranges[order[0]].key->inv_tw;
+  br.post = ranges[order[0]].key->post;
+  br.uni = ranges[order[0]].key->uni;
+  br.ext = ctx->ext;
+  br.ranges = ctx->ranges;
+  br.nranges = (uint32_t)host.size();
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
+                 "blind rotation");
+  if (rc) return rc;
+  // one batched key switch per key over its adjacent ranges
+  size_t a = 0;
+  while (a < order.size()) {
+    size_t b = a;
+    const fs_devkey* key = ranges[order[a]].key;
+    while (b < order.size() && ranges[order[b]].key == key) ++b;
+    const uint64_t first = host[a].first;
+    const uint64_t last = b < order.size() ? host[b].first : total;
+    KsArgs ks{};
+    ks.in = ctx->ext + (size_t)(2 * first) * (P.N + 1);
+    ks.ksk = key->ksk;
+    ks.kskp = key->kskp;
+    ks.plain_add[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
+    ks.plain_add[1] = 0u;
+    ks.nlut = 2;
+    ks.n = P.n;
+    ks.N = P.N;
+    ks.t = P.ks_t;
+    ks.beta = P.ks_base_bit;
+    ks.ranges = ctx->ranges;
+    ks.nranges = (uint32_t)host.size();
+    ks.job0 = 2 * first;
+    rc = launch_rc(launch_keyswitch(ks, (size_t)(2 * (last - first)), st), "key switch");
+    if (rc) return rc;
+    a = b;
+  }
+  return FS_OK;
+}
+
 }  // namespace
 }  // namespace fs
 
@@ -793,125 +908,6 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
       launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
       "blind rotation");
 }
-
-namespace fs {
-namespace {
-// fs_pbs_lif_ranges and its one-rotation form: the blind rotation writes two
-// extracted samples per neuron (rows 2 g and 2 g + 1: Fire, Reset) either
-// from two jobs per neuron or, `many`, from one even-exponent rotation of
-// the interleaved test polynomial; the key switches are the same.
-int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, size_t nranges,
-                   void* stream, bool many) {
-  if (!ctx || !lif || (nranges && !ranges)) return fail(FS_EINVAL, "fs_pbs_lif_ranges: null argument");
-  // order: ranges of one key adjacent (stable), empty ranges dropped
-  std::vector<size_t> order;
-  for (size_t k = 0; k < nranges; ++k) {
-    const fs_lif_range& r = ranges[k];
-    if (r.count == 0) continue;
-    if (!r.key || !r.h || !r.spike2_out || !r.v_out)
-      return fail(FS_EINVAL, "fs_pbs_lif_ranges: null pointer in a range");
-    order.push_back(k);
-  }
-  if (order.empty()) return FS_OK;
-  const fs_params& P = ranges[order[0]].key->prm;
-  for (size_t k : order) {
-    const fs_params& Q = ranges[k].key->prm;
-    if (Q.n != P.n || Q.N != P.N || Q.l != P.l || Q.bg_bit != P.bg_bit || Q.p != P.p ||
-        Q.ks_t != P.ks_t || Q.ks_base_bit != P.ks_base_bit)
-      return fail(FS_EPARAM, "fs_pbs_lif_ranges: keys of different parameter sets");
-    if (ranges[k].key->device != ctx->device)
-      return fail(FS_EPARAM, "fs_pbs_lif_ranges: a key lives on another device");
-  }
-  if (P.ks_t != 8 || P.ks_base_bit != 2)
-    return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: needs the t = 8, base 4 key switch");
-  if (many && P.p > P.N) return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: one rotation needs p <= N");
-  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-    return (uintptr_t)ranges[x].key < (uintptr_t)ranges[y].key;
-  });
-  std::vector<int32_t> fire(P.p), reset(P.p);
-  int rc = fs_lif_luts(lif, P.p, fire.data(), reset.data());
-  if (rc) return rc;
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  DeviceGuard g(ctx->device);
-  hipStream_t st = as_stream(stream);
-  uint32_t* tp[2] = {nullptr, nullptr};
-  if (many) {
-    rc = get_tpoly_two(ctx, P.N, P.p, fire.data(), reset.data(), &tp[0]);
-    tp[1] = tp[0];
-  } else {
-    rc = get_tpoly(ctx, P.N, P.p, fire.data(), &tp[0]);
-    if (!rc) rc = get_tpoly(ctx, P.N, P.p, reset.data(), &tp[1]);
-  }
-  if (rc) return rc;
-  auto& host = ctx->ranges_host;
-  host.clear();
-  uint64_t total = 0;
-  for (size_t k : order) {
-    const fs_lif_range& r = ranges[k];
-    host.push_back(JobRange{r.h, r.spike2_out, r.v_out, r.key->bsk, total});
-    total += r.count;
-  }
-  if (total > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ranges: batch too large");
-  if (ctx->ranges_cap < host.size()) {
-    if (ctx->ranges) FS_HIP(hipFree(ctx->ranges));
-    ctx->ranges = nullptr;
-    ctx->ranges_cap = 0;
-    FS_HIP(hipMalloc(&ctx->ranges, host.size() * sizeof(JobRange)));
-    ctx->ranges_cap = host.size();
-  }
-  FS_HIP(hipMemcpyAsync(ctx->ranges, host.data(), host.size() * sizeof(JobRange),
-                        hipMemcpyHostToDevice, st));
-  const size_t jobs = many ? total : 2 * total;
-  rc = ensure_ext(ctx, 2 * total * (size_t)(P.N + 1));
-  if (rc) return rc;
-  auto vit = ctx->br_variant.find(P.N);
-  const int variant = vit == ctx->br_variant.end() ? 0 : vit->second;
-  BrArgs br{};
-  br.tpoly0 = tp[0];
-  br.tpoly1 = tp[1];
-  br.nlut = many ? 1 : 2;
-  br.even = many ? 1u : 0u;
-  br.n = P.n;
-  br.fwd_tw = ranges[order[0]].key->fwd_tw;  // tables depend on N only
-  br.inv_tw = ranges[order[0]].key->inv_tw;
-  br.post = ranges[order[0]].key->post;
-  br.uni = ranges[order[0]].key->uni;
-  br.ext = ctx->ext;
-  br.ranges = ctx->ranges;
-  br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
-                 "blind rotation");
-  if (rc) return rc;
-  // one batched key switch per key over its adjacent ranges
-  size_t a = 0;
-  while (a < order.size()) {
-    size_t b = a;
-    const fs_devkey* key = ranges[order[a]].key;
-    while (b < order.size() && ranges[order[b]].key == key) ++b;
-    const uint64_t first = host[a].first;
-    const uint64_t last = b < order.size() ? host[b].first : total;
-    KsArgs ks{};
-    ks.in = ctx->ext + (size_t)(2 * first) * (P.N + 1);
-    ks.ksk = key->ksk;
-    ks.kskp = key->kskp;
-    ks.plain_add[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
-    ks.plain_add[1] = 0u;
-    ks.nlut = 2;
-    ks.n = P.n;
-    ks.N = P.N;
-    ks.t = P.ks_t;
-    ks.beta = P.ks_base_bit;
-    ks.ranges = ctx->ranges;
-    ks.nranges = (uint32_t)host.size();
-    ks.job0 = 2 * first;
-    rc = launch_rc(launch_keyswitch(ks, (size_t)(2 * (last - first)), st), "key switch");
-    if (rc) return rc;
-    a = b;
-  }
-  return FS_OK;
-}
-}  // namespace
-}  // namespace fs
 
 int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
                       size_t nranges, void* stream) {

@@ -186,3 +186,30 @@ def test_step_graph_holds_off_the_garbage_collector_while_capturing(monkeypatch)
     with pytest.raises(RuntimeError):
         g2.run()
     assert gc.isenabled()  # restored after a failed capture too
+
+
+# entry points that take the device context first; ones that only set or
+# read host state (destroy, reserve, variants) are covered elsewhere
+_CTX_ENTRY_POINTS = ["fs_lwe_linear", "fs_lwe_conv2d", "fs_lwe_add", "fs_lwe_add_plain",
+                     "fs_pbs", "fs_pbs_lif", "fs_pbs_mspace", "fs_pbs_lif_many_lut",
+                     "fs_pbs_lif_ks_first", "fs_pbs_lif_ranges", "fs_pbs_lif_ranges_many_lut",
+                     "fs_keyswitch", "fs_ntt_polymul", "fs_evk_upload", "fs_ctx_set_br_variant",
+                     "fs_ctx_set_split", "fs_ctx_set_rows", "fs_ctx_reserve"]
+
+
+@pytest.mark.parametrize("name", _CTX_ENTRY_POINTS)
+def test_null_context_is_an_error_code_not_a_crash(name):
+    """Every device entry point checks its arguments before touching a
+    device: a null context returns FS_EINVAL with a message, here on a
+    machine without a GPU."""
+    L = F.lib()
+    fn = getattr(L, name)
+    args = []
+    for t in fn.argtypes:
+        if t in (ctypes.c_int, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t):
+            args.append(t(0))
+        else:
+            args.append(None)
+    rc = fn(*args)
+    assert rc == F.FS_EINVAL, (name, rc)
+    assert L.fs_last_error().decode(), name
