@@ -26,6 +26,13 @@
  *    and no C++ exception crosses this boundary.
  *  - Handles (fs_secret, fs_evk, fs_ctx, fs_devkey) are created by the
  *    library and released by the matching fs_*_free / fs_ctx_destroy.
+ *  - A context (fs_ctx) owns the scratch that its bootstrapping and key
+ *    switching calls write between their kernels (extracted samples, range
+ *    tables).  Calls on one context are safe from any host thread (a mutex
+ *    guards its host state) and are ordered when they share a stream; work
+ *    of one context enqueued on two streams at once races on that scratch.
+ *    Use one context per concurrent stream; device keys may be shared.
+ *    Growing the scratch frees the old buffer, which waits for the device.
  *  - Only k = 1 (one mask polynomial per RLWE sample) is supported.
  */
 #ifndef FHESNN_H
