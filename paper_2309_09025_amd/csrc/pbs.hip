@@ -63,7 +63,9 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // Latency: the key slice of a digit row (16 registers x 2*limbs values per
 // thread) is requested at a point set by PF and consumed after the row's
 // forward transform: PF = 0 after the transform, in two halves; 1 first half
-// before the transform, second after it; 2 the whole slice before.  The
+// before the transform, second after it; 2 the whole slice before; 3 after
+// the transform in quarters (fewest live registers: the N = 2048 job fits
+// two waves per SIMD only this way).  The
 // roots shared by all threads come from the kernel-argument segment and the
 // per-thread ones are requested one round ahead.  WPE is the number of
 // waves per SIMD the register allocation must allow.
@@ -177,7 +179,13 @@ blind_rotate_kernel(BrArgs a) {
       // k mod 2N >= N (one wrap past X^N = -1).
       uint32_t d[16];
       const uint32_t* ac = acc[c];
-      const int kb = t - (int)abar;
+      // The rotated indices and signs are the same for both polynomials; the
+      // empty asm makes the compiler form them again for each one instead of
+      // keeping 3 x 16 registers alive across the step, which cost the N =
+      // 2048 job its second wave per SIMD (and the N = 1024 key-first
+      // variant its spill-free allocation).
+      int kb = t - (int)abar;
+      asm volatile("" : "+v"(kb));
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int k = kb + TP * r;
@@ -189,25 +197,26 @@ blind_rotate_kernel(BrArgs a) {
       for (int lv = 0; lv < L; ++lv) {
         const uint32_t row = key_i + (uint32_t)((c * L + lv) * 16 * TP * G * 8);
         double g[16][G];
-        auto load_half = [&](int h) __attribute__((always_inline)) {
+        constexpr int KCH = PF == 3 ? 4 : 8;  // registers per key request
+        auto load_part = [&](int h) __attribute__((always_inline)) {
 #pragma unroll
-          for (int r = 8 * h; r < 8 * h + 8; ++r)
+          for (int r = KCH * h; r < KCH * h + KCH; ++r)
 #pragma unroll
             for (int q = 0; q < G; q += 2)
               key.at2((uint32_t)t * (G * 8), row + (uint32_t)((r * TP * G + q) * 8), g[r][q],
                       g[r][q + 1]);
         };
-        auto mac_half = [&](int h) __attribute__((always_inline)) {
+        auto mac_part = [&](int h) __attribute__((always_inline)) {
 #pragma unroll
-          for (int r = 8 * h; r < 8 * h + 8; ++r)
+          for (int r = KCH * h; r < KCH * h + KCH; ++r)
 #pragma unroll
             for (int lb = 0; lb < LIMBS; ++lb) {
               p0[lb][r] += mulmod(xd[r], g[r][lb]);
               p1[lb][r] += mulmod(xd[r], g[r][LIMBS + lb]);
             }
         };
-        if constexpr (PF >= 1) load_half(0);
-        if constexpr (PF == 2) load_half(1);
+        if constexpr (PF == 1 || PF == 2) load_part(0);
+        if constexpr (PF == 2) load_part(1);
         const uint32_t sh = 32 - (lv + 1) * BG;
         if constexpr (TAB1) {
           // stage LOGN-1 pairs register r with r + 8: the upper digit times
@@ -226,18 +235,19 @@ blind_rotate_kernel(BrArgs a) {
             xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
         }
         ntt_fwd_reg<LOGN, TAB1>(xd, lds, a.uni, fwd_tw, t);
-        if constexpr (PF == 0) {
-          load_half(0);
-          mac_half(0);
-          load_half(1);
-          mac_half(1);
+        if constexpr (PF == 0 || PF == 3) {
+#pragma unroll
+          for (int h = 0; h < 16 / KCH; ++h) {
+            load_part(h);
+            mac_part(h);
+          }
         } else if constexpr (PF == 1) {
-          load_half(1);
-          mac_half(0);
-          mac_half(1);
+          load_part(1);
+          mac_part(0);
+          mac_part(1);
         } else {
-          mac_half(0);
-          mac_half(1);
+          mac_part(0);
+          mac_part(1);
         }
       }
     }
@@ -783,10 +793,10 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, i
       blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);
     } else {
       switch (variant) {
-        case 0: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1><<<g, 64, 0, st>>>(a); break;
+        case 0: blind_rotate_kernel<10, 3, 7, 1, 2, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1><<<g, 64, 0, st>>>(a); break;
-        case 2: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1><<<g, 64, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 2, 1><<<g, 64, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1><<<g, 64, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1><<<g, 64, 0, st>>>(a); break;
         default: return -2;
       }
     }
@@ -795,10 +805,10 @@ int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, i
       blind_rotate_kernel<11, 2, 10, 2, 0, 1, 2><<<g, 256, 0, st>>>(a);
     } else {
       switch (variant) {
-        case 0: blind_rotate_kernel<11, 2, 10, 2, 0, 1, 1><<<g, 128, 0, st>>>(a); break;
-        case 1: blind_rotate_kernel<11, 2, 10, 2, 2, 1, 1><<<g, 128, 0, st>>>(a); break;
-        case 2: blind_rotate_kernel<11, 2, 10, 2, 1, 1, 1><<<g, 128, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<11, 2, 10, 2, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 0: blind_rotate_kernel<11, 2, 10, 2, 3, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<11, 2, 10, 2, 0, 1, 1><<<g, 128, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<11, 2, 10, 2, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 2, 1, 1, 1><<<g, 128, 0, st>>>(a); break;
         default: return -2;
       }
     }
