@@ -330,17 +330,20 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
 // reduce, four stages, reduce, the remaining one or two stages.  The output
 // is NOT reduced: |x| < 1.14 P (N = 1024) or 1.97 P (N = 2048), which keeps
 // a sum of 2l products with reduced key values below 5 P < 2^53 (the bound
-// check of this schedule is in tests/test_ntt_bounds.py).  The per-thread
-// roots of rounds B and C are requested one round ahead.
-template <int LOGN, bool FIRST_DONE = false>
+// check of this schedule is in tests/test_ntt_bounds.py).  DONE = number of
+// leading stages the caller has already applied (by table, |x| <= 1.5 P
+// after two).  The per-thread roots of rounds B and C are requested one
+// round ahead.
+template <int LOGN, int DONE = 0>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
                                             const Tab& tw, int t) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
+  static_assert(DONE >= 0 && DONE <= 2, "at most two stages by table");
   double wb[R::FB];
   load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb, tw, t);
-  fwd_roundA_uni<LOGN, FIRST_DONE ? LOGN - 2 : LOGN - 1>(x, u);
+  fwd_roundA_uni<LOGN, LOGN - 1 - DONE>(x, u);
   exchange<LOGN, S::LOA, S::LOB>(x, lds, t);
   double wc[R::FC];
   load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);

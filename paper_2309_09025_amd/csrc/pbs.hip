@@ -77,6 +77,45 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
 // of the other's output through LDS, and group c inverse-transforms and
 // updates ACC_c.  Each group reads only its own ACC_c, so the only
 // cross-group synchronisation is the swap.
+// The first two forward stages of a digit row by table (small digit ranges).
+// Stage LOGN-1 pairs registers r and r + 8 with the root i = psi^{brv(1)},
+// stage LOGN-2 pairs r and r + 4 with w = psi^{brv(2)} (r < 8) or
+// psi^{brv(3)} = i psi^{brv(2)} (r >= 8).  For the digits d0..d3 of
+// registers r, r + 4, r + 8, r + 12 (r < 4) the first stage gives
+// d0 +- i d2 and d1 +- i d3, and the second stage's products are
+//   (d1 + i d3) w2 = d1 w2 + d3 w3,   (d1 - i d3) w3 = d1 w3 + d3 w2,
+// so a row needs three tables of d * root over the 2 HALF field values
+// f = d + HALF, stored reduced: tab = [d i | d w2 | d w3].  Outputs are
+// congruent to the arithmetic stages' and bounded by 1.5 P + 64.
+template <uint32_t HALF>
+__device__ __forceinline__ void fill_stage_tables(double* tab, const UniTw& u, int tid, int nt) {
+  constexpr int TW = 2 * HALF;
+  for (int f = tid; f < 3 * TW; f += nt)
+    tab[f] = redc(mulmod((double)(f % TW - (int)HALF), u.fwd[1 + f / TW]));
+}
+
+template <int BG>
+__device__ __forceinline__ void digit_row_two_stages(const uint32_t d[16], uint32_t sh,
+                                                     const double* tab, double xd[16]) {
+  constexpr uint32_t HALF = 1u << (BG - 1);
+  constexpr int TW = 2 * HALF;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double d0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+    const uint32_t f1 = __builtin_amdgcn_ubfe(d[r + 4], sh, BG);
+    const uint32_t f2 = __builtin_amdgcn_ubfe(d[r + 8], sh, BG);
+    const uint32_t f3 = __builtin_amdgcn_ubfe(d[r + 12], sh, BG);
+    const double m1 = tab[f2];
+    const double lo = d0 + m1, hi = d0 - m1;
+    const double ma = tab[TW + f1] + tab[2 * TW + f3];
+    const double mb = tab[2 * TW + f1] + tab[TW + f3];
+    xd[r] = lo + ma;
+    xd[r + 4] = lo - ma;
+    xd[r + 8] = hi + mb;
+    xd[r + 12] = hi - mb;
+  }
+}
+
 template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W>
 __global__ void __launch_bounds__(W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
@@ -89,12 +128,13 @@ blind_rotate_kernel(BrArgs a) {
   static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
   __shared__ double lds_all[W][S::LDS_DOUBLES];
   __shared__ uint32_t acc[2][N];
-  // first forward stage by table: its operands are raw digits, so the
-  // products digit * psi^{brv(1)} take only 2 HALF values, one per field
-  // value f = digit + HALF, stored reduced.  Used for small digit ranges
-  // (Bg = 2^7: 128 entries); at Bg = 2^10 the 8 KiB table measured no gain.
+  // first two forward stages by table (digit_row_two_stages): their
+  // operands are raw digits, so the products take only 2 HALF values per
+  // root.  Used for small digit ranges (Bg = 2^7: 3 x 128 entries, which
+  // still lets 8 jobs share a CU's LDS); at Bg = 2^10 a one-stage table of
+  // 1,024 entries measured no gain.
   constexpr bool TAB1 = 2 * HALF <= 256;
-  __shared__ double stage1[TAB1 ? 2 * HALF : 1];
+  __shared__ double stage1[TAB1 ? 6 * HALF : 1];
 
   const int grp = W == 1 ? 0 : (int)threadIdx.x / TP;  // polynomial group
   const int t = (int)threadIdx.x - grp * TP;
@@ -137,8 +177,7 @@ blind_rotate_kernel(BrArgs a) {
   auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
 
   if constexpr (TAB1) {
-    for (int f = threadIdx.x; f < (int)(2 * HALF); f += W * TP)
-      stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
+    fill_stage_tables<HALF>(stage1, a.uni, threadIdx.x, W * TP);
     if constexpr (W * TP > 64) __syncthreads();  // every wave reads the whole table
   }
 
@@ -219,22 +258,13 @@ blind_rotate_kernel(BrArgs a) {
         if constexpr (PF == 2) load_part(1);
         const uint32_t sh = 32 - (lv + 1) * BG;
         if constexpr (TAB1) {
-          // stage LOGN-1 pairs register r with r + 8: the upper digit times
-          // the root comes from the table
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            const double x0 =
-                (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
-            const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
-            xd[r + 8] = x0 - m;
-            xd[r] = x0 + m;
-          }
+          digit_row_two_stages<BG>(d, sh, stage1, xd);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r)
             xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
         }
-        ntt_fwd_reg<LOGN, TAB1>(xd, lds, a.uni, fwd_tw, t);
+        ntt_fwd_reg<LOGN, TAB1 ? 2 : 0>(xd, lds, a.uni, fwd_tw, t);
         if constexpr (PF == 0 || PF == 3) {
 #pragma unroll
           for (int h = 0; h < 16 / KCH; ++h) {
@@ -344,7 +374,7 @@ blind_rotate_rows_kernel(BrArgs a) {
   __shared__ double lds_all[ROWS][S::LDS_DOUBLES];
   __shared__ double sums[2][LIMBS][16 * TP];  // [output][limb][r][t]
   __shared__ uint32_t acc[2][N];
-  __shared__ double stage1[TAB1 ? 2 * HALF : 1];
+  __shared__ double stage1[TAB1 ? 6 * HALF : 1];
 
   const int grp = (int)threadIdx.x / TP;
   const int t = (int)threadIdx.x - grp * TP;
@@ -377,9 +407,7 @@ blind_rotate_rows_kernel(BrArgs a) {
   auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
 
   const int tid = threadIdx.x;
-  if constexpr (TAB1)
-    for (int f = tid; f < (int)(2 * HALF); f += NT)
-      stage1[f] = redc(mulmod((double)(f - (int)HALF), a.uni.fwd[1]));
+  if constexpr (TAB1) fill_stage_tables<HALF>(stage1, a.uni, tid, NT);
   for (int j = tid; j < 2 * LIMBS * 16 * TP; j += NT) (&sums[0][0][0])[j] = 0.0;
   {
     const uint32_t bbar = mod_switch(ct[n]);
@@ -430,21 +458,14 @@ blind_rotate_rows_kernel(BrArgs a) {
         d[r] = ((val ^ neg) - neg) - ac[t + TP * r] + off;
       }
       if constexpr (TAB1) {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const double x0 =
-              (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
-          const double m = stage1[__builtin_amdgcn_ubfe(d[r + 8], sh, BG)];
-          xd[r + 8] = x0 - m;
-          xd[r] = x0 + m;
-        }
+        digit_row_two_stages<BG>(d, sh, stage1, xd);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
           xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
       }
     }
-    ntt_fwd_reg<LOGN, TAB1>(xd, lds, a.uni, fwd_tw, t);
+    ntt_fwd_reg<LOGN, TAB1 ? 2 : 0>(xd, lds, a.uni, fwd_tw, t);
     if constexpr (PRE < 16) load_key(row, PRE, 16 - PRE);
 #pragma unroll
     for (int r = 0; r < 16; ++r)

@@ -32,19 +32,28 @@ def fwd_schedule(logn):
     return [5, 4, logn - 9]
 
 
+def table_start(dmax):
+    """Bound after the first two stages taken from the digit tables (Bg = 2^7):
+    d0 +- T1[d2] +- (TA[d1] + TB[d3]), each stored entry reduced."""
+    entry = Fr(P, 2) + 1
+    return dmax + 3 * entry
+
+
 def inv_schedule(logn):
     """inverse: stages 0..2 (stage s has 2^-s of its roots equal to 1), then
     3..6, then 7..logn-1, each segment starting from a reduced value."""
     return [(0, 2), (3, 6), (7, logn - 1)]
 
 
-@pytest.mark.parametrize("logn,rows,dmax", [(10, 6, 64), (11, 4, 512)])
-def test_forward_pointwise_inverse_stay_exact(logn, rows, dmax):
-    # forward transform of a digit polynomial
-    A = Fr(dmax)
+@pytest.mark.parametrize("logn,rows,dmax,tables", [(10, 6, 64, True), (10, 6, 64, False),
+                                                (11, 4, 512, False)])
+def test_forward_pointwise_inverse_stay_exact(logn, rows, dmax, tables):
+    # forward transform of a digit polynomial (the first two stages by table
+    # at Bg = 2^7, arithmetic otherwise)
+    A = table_start(dmax) if tables else Fr(dmax)
     segs = fwd_schedule(logn)
     for k, n in enumerate(segs):
-        for _ in range(n):
+        for _ in range(n - 2 if tables and k == 0 else n):
             A = A + prod_bound(A)
             assert A < LIMIT
         if k < len(segs) - 1:
@@ -74,3 +83,13 @@ def test_bounds_are_tight_enough_to_matter():
     for _ in range(6):
         A = A + prod_bound(A)
     assert A > LIMIT
+
+
+def test_table_start_leaves_room_for_exactly_three_stages():
+    """After the two table stages, three arithmetic stages fit below 2^53 and
+    a fourth would not (so the first reduction stays after stage five)."""
+    A = table_start(64)
+    for _ in range(3):
+        A = A + prod_bound(A)
+    assert A < LIMIT
+    assert A + prod_bound(A) > LIMIT
