@@ -299,7 +299,8 @@ def paper_csnn(F, NW, synth, ctx, dk, sk, images=3):
 def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
     """The paper's Poisson-encoded SNN on one image at a time (784 Sign
     bootstrappings per step, FC 784->160 (LIF), FC 160->10 (LIF), T1 = 20),
-    per-step graphs and pipelined with the pixel coding on a second stream."""
+    per-step graphs, pipelined with the pixel coding on a second stream, and
+    with the coding of all steps done first in one launch."""
     cfg = synth.POISSON_SNN
     _, W1, W2 = cfg.data()
     net = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau))
@@ -314,9 +315,18 @@ def poisson_snn(F, NW, synth, ctx, dk, sk, images=2):
         "Poisson-encoded SNN, 1 synthetic 28x28 image (4-bit pixels), 784 Sign "
         "bootstrappings per step, FC 784->160 (LIF) -> FC 160->10 (LIF), "
         "spike-count scores, T1=20", cfg.pbs_count(), m_steps, m_pipe)
+    # the third schedule: every step's pixel coding in one launch, then the
+    # pipelined LIF layers
+    m_ahead = _image_latency(net.run_coded_ahead, args_of, images)
+    rec["coded_ahead_ms"] = round(m_ahead * 1e3, 2)
+    if m_ahead < rec["latency_ms"] / 1e3:
+        rec.update(predictions_per_s=round(1.0 / m_ahead, 3), latency_ms=round(m_ahead * 1e3, 2),
+                   schedule="coded ahead", pbs_per_s=round(cfg.pbs_count() / m_ahead, 1))
     one = NW.PoissonSNN(ctx, dk, W1, W2, NW.LifSpec(cfg.vth, cfg.tau), many_lut=True)
     m_one = _image_latency(lambda x, t: one.run_pipelined(x, t, side_ctx=side), args_of, images)
     rec["one_rotation_per_neuron_pipelined_ms"] = round(m_one * 1e3, 2)
+    m_one_ahead = _image_latency(one.run_coded_ahead, args_of, images)
+    rec["one_rotation_per_neuron_coded_ahead_ms"] = round(m_one_ahead * 1e3, 2)
     return rec
 
 

@@ -473,6 +473,54 @@ class PoissonSNN:
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 
+    def run_coded_ahead(self, px_ct, thresholds, record: bool = False):
+        """run() with the pixel coding of all T steps first: the thresholds
+        are known before the image is processed and the coding reads only the
+        image, so the T x pixels Sign bootstrappings form one batched launch.
+        Then the LIF layers run software-pipelined (wave k bootstraps layer 1
+        at step k and layer 2 at step k-1 in one fs_pbs_lif_ranges launch):
+        T + 1 small launches on the critical path instead of 2 T.  Holds the
+        coded spikes of every step (T x pixels ciphertexts); bit-identical to
+        run()."""
+        c, dk, L = self.ctx, self.dk, self.lif
+        T = len(thresholds)
+        px = self.pixels
+        neg = torch.from_numpy(-np.ascontiguousarray(thresholds, np.int32).reshape(-1)).to("cuda")
+        for b in (self.V1, self.V2, self.score):
+            b.zero_()
+        H0 = px_ct.repeat(T, 1)  # row t * pixels + i: pixel i at step t
+        S0 = torch.empty_like(H0)
+        if T:
+            F.lwe_add_plain(c, self.p, H0, neg, H0)
+            F.pbs(c, dk, self.fire1, H0, S0, keyswitch=True)
+            F.lwe_add_plain(c, self.p, S0, self.ones.repeat(T), S0)
+            self.pbs_count += T * px
+        steps = [{} for _ in range(T)] if record else []
+        for k in range(T + 1 if T else 0):
+            jobs = []
+            if k >= 1:  # layer 2 at step k-1 reads S1 before layer 1 overwrites it
+                F.lwe_linear(c, self.W2, self.S1, self.H2, add=self.V2)
+                jobs.append((dk, self.H2, self.S2, self.V2))
+            if k < T:
+                F.lwe_linear(c, self.W1, S0[k * px:(k + 1) * px], self.H1, add=self.V1)
+                jobs.append((dk, self.H1, self.S1, self.V1))
+            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, many_lut=self.many_lut)
+            self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
+            if k >= 1:
+                F.lwe_add(c, self.score, self.S2, self.score)
+            if record:
+                torch.cuda.synchronize()
+                if k < T:
+                    steps[k]["S0"] = F.to_host(S0[k * px:(k + 1) * px])
+                    steps[k].update({f"{n}1": F.to_host(getattr(self, f"{n}1"))
+                                     for n in ("H", "S", "V")})
+                if k >= 1:
+                    steps[k - 1].update({f"{n}2": F.to_host(getattr(self, f"{n}2"))
+                                         for n in ("H", "S", "V")})
+                    steps[k - 1]["score"] = F.to_host(self.score)
+        torch.cuda.synchronize()
+        return F.to_host(self.score), steps
+
 
 def pbs_count_paper_csnn(T: int) -> int:
     """Bootstrappings per image of the paper's CSNN (Table 1): 2 per LIF

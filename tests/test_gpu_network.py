@@ -159,6 +159,8 @@ def test_paper_and_poisson_mini_many_lut_pipelined_bit_exact(gpu_env, okeys_a):
     for t in range(pc.T):
         for k in ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score"):
             assert np.array_equal(psteps[t][k], posteps[t][k]), (t, k)
+    ascore, _ = pnet.run_coded_ahead(F.to_device(F.encrypt(sk, ppx, synth.SEED_ENC)), thr)
+    assert np.array_equal(ascore, posteps[-1]["score"])
 
 
 def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
@@ -292,7 +294,7 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
     assert np.array_equal(score, total.astype(np.uint32))
 
 
-@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined", "two-streams"])
+@pytest.mark.parametrize("mode", ["eager", "graph", "pipelined", "two-streams", "coded-ahead"])
 def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     """The Poisson-encoded SNN (per step: per-pixel plaintext threshold, one
     Sign bootstrapping per pixel, FC (LIF), FC (LIF), spike counts) at a size
@@ -306,6 +308,8 @@ def test_poisson_snn_mini_bit_exact(gpu_env, okeys_a, mode):
     x = F.to_device(F.encrypt(sk, px, synth.SEED_ENC))
     if mode == "two-streams":  # pixel coding on a second stream and context
         score, steps = net.run_pipelined(x, thr, record=True, side_ctx=F.Context(0))
+    elif mode == "coded-ahead":  # every step's pixel coding in one launch first
+        score, steps = net.run_coded_ahead(x, thr, record=True)
     else:
         run = net.run_pipelined if mode == "pipelined" else net.run
         score, steps = run(x, thr, record=True)
@@ -335,6 +339,7 @@ def test_poisson_snn_full_size_sampled(gpu_env, okeys_a):
     assert net.pbs_count == cfg.pbs_count() == (784 + 2 * 160 + 2 * 10) * cfg.T
     assert np.array_equal(net.run_pipelined(x, thr)[0], score)  # the pipelined schedules
     assert np.array_equal(net.run_pipelined(x, thr, side_ctx=F.Context(0))[0], score)
+    assert np.array_equal(net.run_coded_ahead(x, thr)[0], score)
     octs = O.encrypt(O.SHAPE_A, okeys_a.s, px, synth.SEED_ENC)
     sample = [0, 300, 404, 783]
     plain = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
