@@ -203,15 +203,21 @@ FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
  * previous threshold is stored in *previous unless it is NULL. */
 FS_API int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous);
 
-/* Batches of at most max_jobs jobs (checked before the split threshold)
- * run each job on 2l groups, one per digit row of the external product
- * (Sec. 2.1, RGSW product): a CMux step's critical path is one
- * forward and one inverse transform, for the lowest latency of a single
- * bootstrapping or a few.  Same results.  Default: 2 x the device's
- * compute units.  0 disables it.  *previous as above.  Both thresholds
- * are for N = 1024; at N = 2048 this one counts half and the split one a
- * third (measured crossovers of the wider jobs). */
+/* Batches of at most max_jobs jobs (checked first) run each job on 2l
+ * groups, one per digit row of the external product (Sec. 2.1, RGSW
+ * product): a CMux step's critical path is one forward and one inverse
+ * transform, for the lowest latency of a single bootstrapping or a few.
+ * Same results.  Default: the device's compute units.  0 disables it.
+ * *previous as above.  The thresholds are for N = 1024; at N = 2048 the
+ * split one counts a third (measured crossovers of the wider jobs). */
 FS_API int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous);
+
+/* Batches of at most max_jobs jobs (checked after the row threshold and
+ * before the split one; N = 1024 only) run the two-group form with two
+ * jobs per workgroup, so that every SIMD of a CU holds one wave.  Same
+ * results.  Default: 2 x the device's compute units.  0 disables it.
+ * *previous as above. */
+FS_API int fs_ctx_set_paired(fs_ctx* ctx, size_t max_jobs, size_t* previous);
 
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
  * the exact negacyclic transform on the device; the KSK is copied as is.

@@ -47,7 +47,8 @@ struct fs_ctx {
   // (set at creation to 4 x the device's compute units: below that the
   // one-group kernel leaves SIMDs idle)
   size_t split_max_jobs = 0;
-  size_t rows_max_jobs = 0;  // batches up to this size: one thread group per digit row
+  size_t rows_max_jobs = 0;    // batches up to this size: one thread group per digit row
+  size_t paired_max_jobs = 0;  // then up to this size: two-group jobs in pairs (N = 1024)
   // device copy of the range table of the last multi-key launch
   fs::JobRange* ranges = nullptr;
   size_t ranges_cap = 0;
@@ -242,14 +243,17 @@ int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const 
 }
 
 // thread groups per job for a batch of this size (see launch_blind_rotate).
-// The thresholds are set for N = 1024; at N = 2048 the row kernel holds one
-// job per CU (148 KiB of LDS) and the two-group kernel measured no faster
-// than one group beyond the row kernel's range, hence the scaling.
+// The thresholds are set for N = 1024: one job per CU on the row kernel,
+// then two-group jobs in pairs (one wave per SIMD), then two-group jobs,
+// then one group.  At N = 2048 the row kernel holds one job per CU (148 KiB
+// of LDS), there is no paired form, and the two-group kernel measured no
+// faster than one group beyond the row kernel's range, hence a third of the
+// split threshold.
 int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs) {
-  const size_t rows = N == 2048 ? ctx->rows_max_jobs / 2 : ctx->rows_max_jobs;
-  const size_t split = N == 2048 ? ctx->split_max_jobs / 3 : ctx->split_max_jobs;
-  if (jobs <= rows) return kBrRows;
-  return jobs <= split ? kBrTwo : kBrOne;
+  if (jobs <= ctx->rows_max_jobs) return kBrRows;
+  if (N == 2048) return jobs <= ctx->split_max_jobs / 3 ? kBrTwo : kBrOne;
+  if (jobs <= ctx->paired_max_jobs) return kBrTwoPaired;
+  return jobs <= ctx->split_max_jobs ? kBrTwo : kBrOne;
 }
 
 // blind rotation of jobs = B * nlut, then key switch (or not)
@@ -576,7 +580,8 @@ int fs_ctx_create(int device, fs_ctx** ctx) {
   // measured crossovers (4096 bootstrappings' worth of kernels, N = 1024):
   // one group per digit row wins up to 2 jobs per CU, two groups up to 3
   c->split_max_jobs = 3 * (size_t)cus;
-  c->rows_max_jobs = 2 * (size_t)cus;
+  c->rows_max_jobs = (size_t)cus;
+  c->paired_max_jobs = 2 * (size_t)cus;
   *ctx = c;
   return FS_OK;
 }
@@ -616,6 +621,14 @@ int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (previous) *previous = ctx->rows_max_jobs;
   ctx->rows_max_jobs = max_jobs;
+  return FS_OK;
+}
+
+int fs_ctx_set_paired(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (previous) *previous = ctx->paired_max_jobs;
+  ctx->paired_max_jobs = max_jobs;
   return FS_OK;
 }
 

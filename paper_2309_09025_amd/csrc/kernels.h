@@ -58,6 +58,7 @@ struct BrArgs {
   // multi-key launch: per-range inputs and keys (in and bsk unused)
   const JobRange* ranges;
   uint32_t nranges;
+  uint64_t jobs;          // jobs in the launch (set by launch_blind_rotate)
 };
 
 struct KsArgs {
@@ -82,7 +83,7 @@ int blind_rotate_variants(uint32_t N);
 // Thread groups per job: 1 (large batches; `variant` picks the tuned
 // instance), 2 (one group per input polynomial) or 0 = one group per digit
 // row (2l groups, N = 1024 only; smallest batches, latency).
-enum BrGroups { kBrOne = 1, kBrTwo = 2, kBrRows = 0 };
+enum BrGroups { kBrOne = 1, kBrTwo = 2, kBrRows = 0, kBrTwoPaired = 3 };
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, int groups,
                         hipStream_t st);
 int launch_keyswitch(const KsArgs& a, size_t count, hipStream_t st);

@@ -48,35 +48,6 @@ bsk_to_ntt_kernel(const uint32_t* __restrict__ bsk, double* __restrict__ out, ui
   for (int r = 0; r < 16; ++r) dst[((size_t)r * S::TP + t) * 2 * LIMBS + o * LIMBS + limb] = x[r];
 }
 
-// ---------------------------------------------------------------------------
-// Blind rotation.  One workgroup of TP threads per job (ciphertext, test
-// polynomial); the accumulator lives in LDS in natural order for all n
-// CMux steps.  Step i (a~ = a~_i != 0):
-//   D_c = X^{a~} ACC_c - ACC_c (c = 0 mask, 1 body)
-//   for each gadget level j: digit polynomial -> forward NTT -> multiply by
-//       the two NTT-domain TGSW_i row entries and accumulate
-//   inverse NTT of the two accumulators -> exact integers -> ACC_c +=
-// Initialization ACC = (0, X^{-b~} v) and sample extraction of
-// coefficient 0 are fused at both ends; the key switch of the batch follows
-// in keyswitch_mfma_kernel.
-//
-// Latency: the key slice of a digit row (16 registers x 2*limbs values per
-// thread) is requested at a point set by PF and consumed after the row's
-// forward transform: PF = 0 after the transform, in two halves; 1 first half
-// before the transform, second after it; 2 the whole slice before; 3 after
-// the transform in quarters (fewest live registers: the N = 2048 job fits
-// two waves per SIMD only this way).  The
-// roots shared by all threads come from the kernel-argument segment and the
-// per-thread ones are requested one round ahead.  WPE is the number of
-// waves per SIMD the register allocation must allow.
-//
-// W = 2 splits one job over two polynomial groups of TP threads (two waves
-// at N = 1024), for batches too small to fill the device: group c
-// decomposes and transforms the digits of D_c only, accumulating partial
-// products for both outputs; once per step the groups swap the partial sums
-// of the other's output through LDS, and group c inverse-transforms and
-// updates ACC_c.  Each group reads only its own ACC_c, so the only
-// cross-group synchronisation is the swap.
 // The first two forward stages of a digit row by table (small digit ranges).
 // Stage LOGN-1 pairs registers r and r + 8 with the root i = psi^{brv(1)},
 // stage LOGN-2 pairs r and r + 4 with w = psi^{brv(2)} (r < 8) or
@@ -116,8 +87,44 @@ __device__ __forceinline__ void digit_row_two_stages(const uint32_t d[16], uint3
   }
 }
 
-template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W>
-__global__ void __launch_bounds__(W * NttShape<LOGN>::TP, WPE)
+// ---------------------------------------------------------------------------
+// Blind rotation.  One workgroup of TP threads per job (ciphertext, test
+// polynomial); the accumulator lives in LDS in natural order for all n
+// CMux steps.  Step i (a~ = a~_i != 0):
+//   D_c = X^{a~} ACC_c - ACC_c (c = 0 mask, 1 body)
+//   for each gadget level j: digit polynomial -> forward NTT -> multiply by
+//       the two NTT-domain TGSW_i row entries and accumulate
+//   inverse NTT of the two accumulators -> exact integers -> ACC_c +=
+// Initialization ACC = (0, X^{-b~} v) and sample extraction of
+// coefficient 0 are fused at both ends; the key switch of the batch follows
+// in keyswitch_mfma_kernel.
+//
+// Latency: the key slice of a digit row (16 registers x 2*limbs values per
+// thread) is requested at a point set by PF and consumed after the row's
+// forward transform: PF = 0 after the transform, in two halves; 1 first half
+// before the transform, second after it; 2 the whole slice before; 3 after
+// the transform in quarters (fewest live registers: the N = 2048 job fits
+// two waves per SIMD only this way).  The roots shared by all threads come
+// from the kernel-argument segment and the per-thread ones are requested one
+// round ahead.  WPE is the number of waves per SIMD the register allocation
+// must allow.
+//
+// W = 2 splits one job over two polynomial groups of TP threads (two waves
+// at N = 1024), for batches too small to fill the device: group c
+// decomposes and transforms the digits of D_c only, accumulating partial
+// products for both outputs; once per step the groups swap the partial sums
+// of the other's output through LDS, and group c inverse-transforms and
+// updates ACC_c.  Each group reads only its own ACC_c, so the only
+// cross-group synchronisation is the swap.
+//
+// JPW = 2 puts two such jobs in one workgroup (four waves at N = 1024), so
+// that a batch of up to 2 x CUs jobs occupies every SIMD once: two separate
+// two-wave workgroups on one CU may share two of its SIMDs.  Both jobs then
+// pass the same workgroup barriers, so neither skips a step (a step with
+// a~_i = 0 adds zero, so the bits are the same); the second half of the
+// last workgroup of an odd batch repeats the last job without writing.
+template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W, int JPW = 1>
+__global__ void __launch_bounds__(JPW * W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
   constexpr int N = S::N, TP = S::TP, ROWS = 2 * L;
@@ -125,9 +132,10 @@ blind_rotate_kernel(BrArgs a) {
   constexpr uint32_t NU = LOGN + 1;  // log2(2N)
   constexpr int G = 2 * LIMBS;       // key values per slot and digit row
   static_assert(W == 1 || W == 2, "one or two polynomial groups per job");
+  static_assert(JPW == 1 || (JPW == 2 && W == 2), "paired jobs use two groups each");
   static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
-  __shared__ double lds_all[W][S::LDS_DOUBLES];
-  __shared__ uint32_t acc[2][N];
+  __shared__ double lds_all[JPW * W][S::LDS_DOUBLES];
+  __shared__ uint32_t acc_all[JPW][2][N];
   // first two forward stages by table (digit_row_two_stages): their
   // operands are raw digits, so the products take only 2 HALF values per
   // root.  Used for small digit ranges (Bg = 2^7: 3 x 128 entries, which
@@ -136,10 +144,16 @@ blind_rotate_kernel(BrArgs a) {
   constexpr bool TAB1 = 2 * HALF <= 256;
   __shared__ double stage1[TAB1 ? 6 * HALF : 1];
 
-  const int grp = W == 1 ? 0 : (int)threadIdx.x / TP;  // polynomial group
-  const int t = (int)threadIdx.x - grp * TP;
-  double* lds = lds_all[grp];
-  const size_t job = blockIdx.x;
+  // job of the workgroup (uniform per wave, so kept in a scalar register)
+  const int js = JPW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x / (W * TP));
+  const int ltid = (int)threadIdx.x - js * W * TP;             // thread within the job
+  const int grp = W == 1 ? 0 : ltid / TP;                      // polynomial group
+  const int t = ltid - grp * TP;
+  double* lds = lds_all[js * W + grp];
+  uint32_t(*acc)[N] = acc_all[js];
+  size_t job = (size_t)blockIdx.x * JPW + js;
+  const bool writes = JPW == 1 || job < a.jobs;
+  if (!writes) job = a.jobs - 1;
   const uint32_t n = a.n;
   // ciphertext and program function of this job (nlut is 1 or 2: shifts,
   // which stay on the scalar unit, unlike a 64-bit division)
@@ -177,8 +191,8 @@ blind_rotate_kernel(BrArgs a) {
   auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
 
   if constexpr (TAB1) {
-    fill_stage_tables<HALF>(stage1, a.uni, threadIdx.x, W * TP);
-    if constexpr (W * TP > 64) __syncthreads();  // every wave reads the whole table
+    fill_stage_tables<HALF>(stage1, a.uni, threadIdx.x, JPW * W * TP);
+    if constexpr (JPW * W * TP > 64) __syncthreads();  // every wave reads the whole table
   }
 
   // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
@@ -202,7 +216,8 @@ blind_rotate_kernel(BrArgs a) {
 
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t abar = mod_switch(ct[i]);
-    if (abar == 0) continue;  // X^0 ACC - ACC = 0: every digit is zero
+    // X^0 ACC - ACC = 0: every digit is zero (paired jobs keep in step)
+    if (JPW == 1 && abar == 0) continue;
     double p0[LIMBS][16], p1[LIMBS][16], xd[16];
 #pragma unroll
     for (int lb = 0; lb < LIMBS; ++lb)
@@ -292,7 +307,7 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) lds[r * TP + t] = mine_other[r];
         __syncthreads();
-        const double* theirs = lds_all[1 - grp];
+        const double* theirs = lds_all[js * W + 1 - grp];
 #pragma unroll
         for (int r = 0; r < 16; ++r) mine[r] += theirs[r * TP + t];
       }
@@ -323,7 +338,8 @@ blind_rotate_kernel(BrArgs a) {
   // Sample Extraction of coefficient k (negacyclic reversal of the mask):
   // a'_j = a_{k-j} for j <= k, -a_{N+k-j} otherwise; b' = b_k.  Coefficient
   // 0 always, coefficient 1 too when two functions share the rotation.
-  const int tid = threadIdx.x;
+  const int tid = ltid;
+  if (!writes) return;
 #pragma unroll
   for (uint32_t k = 0; k < 2; ++k) {
     if (k > even) break;
@@ -800,12 +816,17 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 // N = 1024 and (0, 1) at N = 2048.
 int blind_rotate_variants(uint32_t N) { return N == 1024 || N == 2048 ? 4 : 0; }
 
-int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, int groups,
+int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant, int groups,
                         hipStream_t st) {
   if (jobs == 0) return 0;
+  BrArgs a = args;
+  a.jobs = jobs;
   const dim3 g((uint32_t)jobs);
-  const bool split = groups == kBrTwo;
-  if (groups == kBrRows) {
+  const bool split = groups == kBrTwo || (groups == kBrTwoPaired && N != 1024);
+  if (groups == kBrTwoPaired && N == 1024) {
+    // two jobs of two groups per workgroup: every SIMD of a CU holds one wave
+    blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2, 2><<<dim3((uint32_t)((jobs + 1) / 2)), 256, 0, st>>>(a);
+  } else if (groups == kBrRows) {
     if (N == 1024) blind_rotate_rows_kernel<10, 3, 7, 1><<<g, 6 * 64, 0, st>>>(a);
     else if (N == 2048) blind_rotate_rows_kernel<11, 2, 10, 2><<<g, 4 * 128, 0, st>>>(a);
     else return -1;

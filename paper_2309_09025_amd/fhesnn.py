@@ -70,6 +70,7 @@ SIGNATURES = {
     "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
     "fs_ctx_set_split": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "fs_ctx_set_rows": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "fs_ctx_set_paired": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "fs_evk_export": (_int, [_vp, _u32p, _u32p]),
     "fs_evk_params": (_int, [_vp, _PP]),
     "fs_secret_free": (None, [_vp]),
@@ -314,20 +315,31 @@ class Context:
         _check("fs_ctx_set_rows", lib().fs_ctx_set_rows(self.h, max_jobs, ctypes.byref(prev)))
         return prev.value
 
+    def set_paired(self, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs (after the row threshold) use two
+        thread groups per job and two jobs per workgroup (N = 1024); returns
+        the previous threshold."""
+        prev = ctypes.c_size_t()
+        _check("fs_ctx_set_paired", lib().fs_ctx_set_paired(self.h, max_jobs, ctypes.byref(prev)))
+        return prev.value
+
     def groups(self, mode: str):
-        """Context manager forcing the thread groups per job: "one", "two"
-        or "rows" (restores the thresholds on exit)."""
+        """Context manager forcing the thread groups per job: "one", "two",
+        "paired" (two groups, two jobs per workgroup; N = 1024) or "rows"
+        (restores the thresholds on exit)."""
         import contextlib
 
         @contextlib.contextmanager
         def cm():
             big = 1 << 40
-            rows, split = {"one": (0, 0), "two": (0, big), "rows": (big, 0)}[mode]
-            pr, ps = self.set_rows(rows), self.set_split(split)
+            rows, paired, split = {"one": (0, 0, 0), "two": (0, 0, big), "paired": (0, big, 0),
+                                   "rows": (big, 0, 0)}[mode]
+            pr, pp, ps = self.set_rows(rows), self.set_paired(paired), self.set_split(split)
             try:
                 yield self
             finally:
                 self.set_rows(pr)
+                self.set_paired(pp)
                 self.set_split(ps)
         return cm()
 

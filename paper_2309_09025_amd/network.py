@@ -473,7 +473,7 @@ class PoissonSNN:
         torch.cuda.synchronize()
         return F.to_host(self.score), steps
 
-    def run_coded_ahead(self, px_ct, thresholds, record: bool = False):
+    def run_coded_ahead(self, px_ct, thresholds, record: bool = False, chain_mode=None):
         """run() with the pixel coding of all T steps first: the thresholds
         are known before the image is processed and the coding reads only the
         image, so the T x pixels Sign bootstrappings form one batched launch.
@@ -481,7 +481,8 @@ class PoissonSNN:
         at step k and layer 2 at step k-1 in one fs_pbs_lif_ranges launch):
         T + 1 small launches on the critical path instead of 2 T.  Holds the
         coded spikes of every step (T x pixels ciphertexts); bit-identical to
-        run()."""
+        run().  chain_mode: thread-group form of the LIF launches (see
+        Context.groups; None = chosen by batch size)."""
         c, dk, L = self.ctx, self.dk, self.lif
         T = len(thresholds)
         px = self.pixels
@@ -504,7 +505,8 @@ class PoissonSNN:
             if k < T:
                 F.lwe_linear(c, self.W1, S0[k * px:(k + 1) * px], self.H1, add=self.V1)
                 jobs.append((dk, self.H1, self.S1, self.V1))
-            F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, many_lut=self.many_lut)
+            with c.groups(chain_mode) if chain_mode else contextlib.nullcontext():
+                F.pbs_lif_ranges(c, L.v_th, L.tau, jobs, many_lut=self.many_lut)
             self.pbs_count += sum(2 * j[1].shape[0] for j in jobs)
             if k >= 1:
                 F.lwe_add(c, self.score, self.S2, self.score)

@@ -129,8 +129,9 @@ def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, varian
 @pytest.mark.parametrize("shape,count,keyswitch", [(0, 5, True), (0, 70, True), (0, 9, False),
                                                      (0, 1, True), (1, 3, True), (1, 66, True)])
 def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, keyswitch):
-    """One thread group per digit row (N = 1024), two per job and one per
-    job give the oracle's bits, with and without the key switch."""
+    """One thread group per digit row, two per job (alone or two jobs per
+    workgroup, odd counts included) and one per job give the oracle's bits,
+    with and without the key switch."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(shape)
     ok = okeys_a if shape == 0 else okeys_b
@@ -138,7 +139,7 @@ def test_split_blind_rotation_bit_exact(gpu_env, okeys_a, okeys_b, shape, count,
     f = O.lut_reset(P.p, 4, 2)
     width = P.n + 1 if keyswitch else P.N + 1
     want = O.pbs(ok, O.test_poly(P.N, P.p, f), ct, keyswitch=keyswitch)
-    for mode in ("rows", "two", "one"):
+    for mode in ("rows", "paired", "two", "one"):
         with ctx.groups(mode):
             out = torch.zeros((count, width), dtype=torch.int32, device="cuda")
             F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=keyswitch)
@@ -201,8 +202,8 @@ def test_pbs_lif_batched_key_switch_bit_exact(gpu_env, okeys_a):
 
 
 @pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
-                                              (0, 21, "rows"), (0, 600, "one"), (1, 3, "two"),
-                                              (1, 5, "one"), (1, 4, "rows")])
+                                              (0, 21, "rows"), (0, 600, "one"), (0, 19, "paired"),
+                                              (1, 3, "two"), (1, 5, "one"), (1, 4, "rows")])
 def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Key switch of LWE_z(H), then Fire and Reset rotations extracted
     straight into the two outputs under z (one- and two-group kernels,
@@ -231,8 +232,8 @@ def test_pbs_lif_key_switch_first_bit_exact(gpu_env, okeys_a, okeys_b, shape, co
 
 
 @pytest.mark.parametrize("shape,count,mode", [(0, 1, "two"), (0, 37, "two"), (0, 37, "one"),
-                                              (0, 13, "rows"), (0, 1100, "one"), (1, 3, "two"),
-                                              (1, 5, "one"), (1, 4, "rows")])
+                                              (0, 13, "rows"), (0, 1100, "one"), (0, 23, "paired"),
+                                              (1, 3, "two"), (1, 5, "one"), (1, 4, "rows")])
 def test_pbs_lif_many_lut_bit_exact(gpu_env, okeys_a, okeys_b, shape, count, mode):
     """Fire and Reset from one even-exponent rotation per neuron (one- and
     two-group kernels, ragged batches, both shapes): sampled neurons equal

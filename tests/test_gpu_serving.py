@@ -24,7 +24,8 @@ def clients(gpu_env):
     return out
 
 
-@pytest.mark.parametrize("variant,mode", [(0, "rows"), (0, "two"), (1, "one"), (2, "one")])
+@pytest.mark.parametrize("variant,mode", [(0, "rows"), (0, "two"), (0, "paired"), (1, "one"),
+                                          (2, "one")])
 def test_pbs_lif_ranges_equals_one_call_per_range(gpu_env, clients, okeys_a, variant, mode):
     """Multi-key launch == one launch per range == oracle, on the row and
     two-group kernels (small batches) and on two one-group variants."""

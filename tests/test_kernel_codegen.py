@@ -53,9 +53,9 @@ def _br(usage, args):
     return mangled, usage[mangled]
 
 
-@pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1), (10, 3, 7, 1, 1, 2, 1),
-                                  (10, 3, 7, 1, 2, 2, 1), (10, 3, 7, 1, 1, 2, 2),
-                                  (11, 2, 10, 2, 3, 2, 1)])
+@pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1, 1), (10, 3, 7, 1, 1, 2, 1, 1),
+                                  (10, 3, 7, 1, 2, 2, 1, 1), (10, 3, 7, 1, 1, 2, 2, 1),
+                                  (10, 3, 7, 1, 1, 2, 2, 2), (11, 2, 10, 2, 3, 2, 1, 1)])
 def test_two_wave_kernels_have_no_scratch(compiled, args):
     usage, _ = compiled
     _, u = _br(usage, args)
