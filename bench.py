@@ -493,6 +493,7 @@ def main():
     stream = torch.cuda.current_stream()
     from paper_2309_09025_amd import tune
     variant, variant_ms = tune.tune_blind_rotation(ctx, dk, B, use_cache=not args.retune)
+    group_limits, _ = tune.tune_groups(ctx, dk, use_cache=not args.retune)
 
     def step(ev=None):
         # blind rotation + sample extraction, then the batched key switch:
@@ -547,6 +548,8 @@ def main():
         "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
         "kernel_ms": round(br_avg, 4),
         "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
+        # batch-size thresholds of the thread-group forms (tuned, in jobs)
+        "group_limits": dict(zip(("rows", "paired", "split"), group_limits)),
     }
 
     cpu = None

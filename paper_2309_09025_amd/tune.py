@@ -87,3 +87,74 @@ def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
         cache[key] = {"variant": best, "ms": {str(k): round(t, 4) for k, t in times.items()}}
         _store(cache)
     return best, times
+
+
+# Thread-group forms in the order the library checks their thresholds.
+FORMS = ("rows", "paired", "two", "one")
+
+
+def thresholds_from_best(best, cus: int):
+    """Batch-size thresholds (rows_max, paired_max, split_max) from the best
+    form of each interval ((k-1) CUs, k CUs], k = 1, 2, ...: the library
+    tries the forms in FORMS order, so each threshold ends the leading run
+    of intervals whose best form is that one or an earlier one."""
+    limits = {}
+    k = 0
+    for form in FORMS[:-1]:
+        while k < len(best) and FORMS.index(best[k]) <= FORMS.index(form):
+            k += 1
+        limits[form] = k * cus
+    return limits["rows"], limits["paired"], limits["two"]
+
+
+def tune_groups(ctx: F.Context, dk: F.DevKey, intervals: int = 4, reps: int = 2,
+                use_cache: bool = True, store: bool = True):
+    """Time every thread-group form at k x CUs jobs (the largest batch of
+    each interval; the forms' times are steps at multiples of the CU count)
+    for k = 1..intervals, set the resulting thresholds on ctx and return
+    (thresholds, {jobs: {form: ms}}).  The paired form exists at N = 1024
+    only (elsewhere it falls back to two groups and is skipped)."""
+    import torch
+    P = dk.params
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    key = f"{arch_name()}|N={P.N}|l={P.l}|bg={P.bg_bit}|groups|cus={cus}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        best = cache[key]["best"]
+        times = {int(j): v for j, v in cache[key]["ms"].items()}
+    else:
+        forms = FORMS if P.N == 1024 else tuple(f for f in FORMS if f != "paired")
+        g = np.random.Generator(np.random.PCG64(4321))
+        lut = np.where(np.arange(P.p) < P.p // 2, 1, -1).astype(np.int32)
+        stream = torch.cuda.current_stream()
+        times, best = {}, []
+        for k in range(1, intervals + 1):
+            jobs = k * cus
+            x = F.to_device(g.integers(0, 2 ** 32, size=(jobs, P.n + 1),
+                                       dtype=np.uint64).astype(np.uint32))
+            ext = F.empty_ct(jobs, P.N + 1)
+            times[jobs] = {}
+            for form in forms:
+                with ctx.groups(form):
+                    F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)  # warm
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                times[jobs][form] = round(e0.elapsed_time(e1) / reps, 4)
+            best.append(min(times[jobs], key=times[jobs].get))
+        if store:
+            cache = _load()
+            cache[key] = {"best": best, "ms": {str(j): v for j, v in times.items()}}
+            _store(cache)
+    rows, paired, split = thresholds_from_best(best, cus)
+    if P.N == 2048:  # the library counts a third of the split threshold there
+        split *= 3
+    ctx.set_rows(rows)
+    ctx.set_paired(paired)
+    ctx.set_split(split)
+    return (rows, paired, split), times

@@ -348,3 +348,28 @@ def test_shape_b_lif_batched_key_switch_bit_exact(gpu_env, okeys_b):
     spikes, vnew = O.lif_step(okeys_b, 4, 2, ct[idx])
     assert np.array_equal(_host(s2)[idx], spikes)
     assert np.array_equal(_host(vv)[idx], vnew)
+
+
+def test_group_form_tuner_sets_ordered_thresholds(gpu_env, okeys_a):
+    """The autotuner times the thread-group forms at 1 and 2 x CUs jobs on a
+    context of its own and sets ordered thresholds; a batch in each tuned
+    interval still gives the oracle's bits."""
+    from paper_2309_09025_amd import tune
+    _, get = gpu_env
+    P, sk, evk, _ = get(0)
+    ctx = F.Context(0)
+    dk = F.evk_upload(ctx, evk)
+    (rows, paired, split), times = tune.tune_groups(ctx, dk, intervals=2, reps=1,
+                                                    use_cache=False, store=False)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert sorted(times) == [cus, 2 * cus]
+    assert all(ms > 0 for t in times.values() for ms in t.values())
+    assert 0 <= rows <= paired <= split <= 2 * cus
+    f = O.lut_reset(P.p, 4, 2)
+    for count in (3, cus + 1):
+        m, ct = _pbs_inputs(P, sk, okeys_a, count, first=7000 + count)
+        out = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
+        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=True)
+        idx = sorted({0, count // 2, count - 1})
+        want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=True)
+        assert np.array_equal(_host(out)[idx], want), count
