@@ -46,9 +46,17 @@ def _store(cache):
     os.replace(tmp, CACHE)
 
 
-def arch_name() -> str:
+def _check_device(ctx: F.Context):
+    """The timing buffers and stream are torch's current device's."""
     import torch
-    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    if torch.cuda.current_device() != ctx.device:
+        raise ValueError(f"tuning a context of device {ctx.device} needs it to be torch's "
+                         f"current device (now {torch.cuda.current_device()})")
+
+
+def arch_name(device: int = 0) -> str:
+    import torch
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
 
 
 def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
@@ -57,7 +65,8 @@ def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
     launch; sets it on ctx and returns (variant, {variant: ms})."""
     import torch
     P = dk.params
-    key = _key(arch_name(), P, jobs)
+    _check_device(ctx)
+    key = _key(arch_name(ctx.device), P, jobs)
     cache = _load() if use_cache else {}
     if key in cache:
         best = int(cache[key]["variant"])
@@ -116,8 +125,9 @@ def tune_groups(ctx: F.Context, dk: F.DevKey, intervals: int = 4, reps: int = 2,
     only (elsewhere it falls back to two groups and is skipped)."""
     import torch
     P = dk.params
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    key = f"{arch_name()}|N={P.N}|l={P.l}|bg={P.bg_bit}|groups|cus={cus}"
+    _check_device(ctx)
+    cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    key = f"{arch_name(ctx.device)}|N={P.N}|l={P.l}|bg={P.bg_bit}|groups|cus={cus}"
     cache = _load() if use_cache else {}
     if key in cache:
         best = cache[key]["best"]
