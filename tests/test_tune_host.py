@@ -20,3 +20,22 @@ def test_an_earlier_form_inside_a_later_run_does_not_end_it():
 
 def test_no_intervals_disable_every_small_batch_form():
     assert tune.thresholds_from_best([], 256) == (0, 0, 0)
+
+
+def test_committed_cache_is_well_formed():
+    """Every cached variant choice names an existing variant and was the
+    fastest of its timings; every cached form list names known forms."""
+    import json
+    with open(tune.CACHE) as fh:
+        cache = json.load(fh)
+    assert cache
+    for key, rec in cache.items():
+        if "|groups|" in key:
+            assert rec["best"] and set(rec["best"]) <= set(tune.FORMS), key
+            for jobs, ms in rec["ms"].items():
+                assert rec["best"][sorted(map(int, rec["ms"])).index(int(jobs))] == \
+                    min(ms, key=ms.get), (key, jobs)
+        else:
+            ms = {int(v): t for v, t in rec["ms"].items()}
+            assert sorted(ms) == list(range(4)), key  # four variants per ring degree
+            assert rec["variant"] == min(ms, key=ms.get), key
