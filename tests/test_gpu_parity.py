@@ -373,3 +373,21 @@ def test_group_form_tuner_sets_ordered_thresholds(gpu_env, okeys_a):
         idx = sorted({0, count // 2, count - 1})
         want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=True)
         assert np.array_equal(_host(out)[idx], want), count
+
+
+@pytest.mark.parametrize("mode", ["paired", "two"])
+def test_two_group_forms_beyond_one_workgroup_per_cu(gpu_env, okeys_a, mode):
+    """601 jobs (an odd count) forced onto the two-group forms: more
+    workgroups than CUs, so several share a CU; sampled rows (first, middle,
+    the repeated last job of the paired form) equal the oracle's."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    count = 601
+    m, ct = _pbs_inputs(P, sk, okeys_a, count, first=9100)
+    f = O.lut_fire(P.p, 4)
+    out = torch.zeros((count, P.n + 1), dtype=torch.int32, device="cuda")
+    with ctx.groups(mode):
+        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=True)
+    idx = [0, 300, count - 2, count - 1]
+    want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=True)
+    assert np.array_equal(_host(out)[idx], want)
