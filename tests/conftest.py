@@ -25,6 +25,19 @@ def okeys_a():
 
 
 @pytest.fixture(scope="session")
+def okeys_a_quiet():
+    """Oracle keys, shape A, seed 1, with every noise deviation set to 0.
+    The only errors left are the roundings of the modulus switch (std
+    2^-8.6 at the blind rotation's input, 6.2 sigma inside a message
+    window), the gadget decomposition and the key switch (about 2^-12.9 at
+    a bootstrapping's output), so a layer input summing dozens of
+    bootstrapped spikes still decrypts to its plaintext value."""
+    from dataclasses import replace
+    P = replace(O.SHAPE_A, sigma_lwe=0.0, sigma_bsk=0.0, sigma_ksk=0.0)
+    return O.keygen(P, synth.SEED_KEYS)
+
+
+@pytest.fixture(scope="session")
 def okeys_b():
     """Oracle keys, shape B (N = 2048), seed 1."""
     return O.keygen(O.SHAPE_B, synth.SEED_KEYS)

@@ -133,3 +133,93 @@ def test_poisson_snn_oracle_spikes_equal_plaintext(okeys_a):
         assert np.array_equal(steps[t]["H2"], O.lwe_linear(W2, steps[t]["S1"], add=V2prev))
     assert any(psteps[t]["S0"].any() for t in range(cfg.T))  # some pixel spiked
 
+
+
+# ---------------------------------------------------------------------------
+# Whole networks against the plaintext integer SNN.  With real noise the
+# layers after the first sum dozens of bootstrapped outputs (std 2^-8.15
+# each) and no longer decrypt reliably, so the compositions are pinned with
+# noiseless keys (okeys_a_quiet): every ciphertext of every step, the score
+# accumulators included, must decrypt to the mod-p recurrence of Theorem 3.1
+# (Eq. DiscretEquation) with WeightSum layers (Sec. 4.1) and scores summed
+# over the T steps.  A wrong operand anywhere (a missing V, a layer fed the
+# wrong spikes, a score not accumulated) changes some decryption; the
+# checks below also make sure each instance exercises those terms.
+
+def _decrypts_to(keys, ct, plain, p):
+    return np.array_equal(O.decrypt(p, keys.s, ct), O.centred(p, plain))
+
+
+def _exercises(psteps, V, S, score):
+    """The instance makes the recurrence matter: some potential V survives
+    a step, some neuron of the layer spikes and some does not, and the
+    score changes after the first step."""
+    assert any(np.any(st[V] % 32 != 0) for st in psteps[:-1]), V
+    spikes = np.concatenate([st[S] for st in psteps])
+    assert np.any(spikes == 2) and np.any(spikes == 0), S
+    assert any(not np.array_equal(psteps[t][score], psteps[0][score])
+               for t in range(1, len(psteps))), score
+
+
+def test_conv_snn_oracle_equals_plaintext_at_every_step(okeys_a_quiet):
+    """conv_snn_run (conv (LIF) -> FC (LIF) -> FC score accumulators) against
+    plain_conv_snn_run, every state and the scores, T = 3."""
+    K = okeys_a_quiet
+    P = K.params
+    cfg = synth.ConvSNN(H=6, Wd=6, Co=2, K=3, stride=2, pad=1, hidden=4, classes=3,
+                        w_lo=-2, w_hi=2, T=3)
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    ct = O.encrypt(P, K.s, px, synth.SEED_ENC)
+    I1, steps = O.conv_snn_run(K, ct, Wc, W1, W2, geom, cfg.vth, cfg.tau, cfg.T)
+    pI1, psteps = O.plain_conv_snn_run(P.p, px, Wc, W1, W2, geom, cfg.vth, cfg.tau, cfg.T)
+    assert _decrypts_to(K, I1, pI1, P.p)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert _decrypts_to(K, steps[t][k], psteps[t][k], P.p), (t, k)
+    _exercises(psteps, "V1", "S1", "score")
+    _exercises(psteps, "V2", "S2", "score")
+    # the score is the sum over steps of W2 2S[t], not the last step's alone
+    tot = sum(np.asarray(W2, np.int64) @ psteps[t]["S2"] for t in range(cfg.T)) % P.p
+    assert np.array_equal(psteps[-1]["score"], tot)
+
+
+def test_paper_csnn_oracle_equals_plaintext_at_every_step(okeys_a_quiet):
+    """paper_csnn_run (conv (LIF) -> sum pool -> FC (LIF) -> FC (LIF), spike
+    counts as scores) against plain_paper_csnn_run, every state and the
+    scores."""
+    K = okeys_a_quiet
+    P = K.params
+    cfg = synth.PaperCSNN(H=8, Wd=8, Co=2, K=4, stride=2, pad=1, hidden=4, classes=3,
+                          w_lo=-3, w_hi=3, T=3)
+    px, Wc, W1, W2 = cfg.data()
+    geom = (cfg.Ci, cfg.H, cfg.Wd, cfg.stride, cfg.pad)
+    ct = O.encrypt(P, K.s, px, synth.SEED_ENC)
+    _, steps = O.paper_csnn_run(K, ct, Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau, cfg.T)
+    _, psteps = O.plain_paper_csnn_run(P.p, px, Wc, W1, W2, geom, cfg.pool, cfg.vth, cfg.tau,
+                                       cfg.T)
+    for t in range(cfg.T):
+        for k in ("H1", "S1", "V1", "H2", "S2", "V2", "H3", "S3", "V3", "score"):
+            assert _decrypts_to(K, steps[t][k], psteps[t][k], P.p), (t, k)
+    _exercises(psteps, "V2", "S2", "score")
+    tot = sum(psteps[t]["S3"] for t in range(cfg.T)) % P.p
+    assert np.array_equal(psteps[-1]["score"], tot)
+
+
+def test_poisson_snn_oracle_equals_plaintext_at_every_step(okeys_a_quiet):
+    """poisson_snn_run (Sign coding -> FC (LIF) -> FC (LIF), spike counts as
+    scores) against plain_poisson_snn_run, every state and the scores."""
+    K = okeys_a_quiet
+    P = K.params
+    cfg = synth.PoissonSNN(H=4, Wd=4, hidden=4, classes=3, w_lo=-3, w_hi=3, T=3)
+    px, W1, W2 = cfg.data()
+    thr = cfg.thresholds()
+    ct = O.encrypt(P, K.s, px, synth.SEED_ENC)
+    steps = O.poisson_snn_run(K, ct, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    psteps = O.plain_poisson_snn_run(P.p, px, thr, W1, W2, cfg.vth, cfg.tau, cfg.T)
+    for t in range(cfg.T):
+        for k in ("S0", "H1", "S1", "V1", "H2", "S2", "V2", "score"):
+            assert _decrypts_to(K, steps[t][k], psteps[t][k], P.p), (t, k)
+    _exercises(psteps, "V1", "S1", "score")
+    tot = sum(psteps[t]["S2"] for t in range(cfg.T)) % P.p
+    assert np.array_equal(psteps[-1]["score"], tot)
