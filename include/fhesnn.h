@@ -32,7 +32,11 @@
  *    guards its host state) and are ordered when they share a stream; work
  *    of one context enqueued on two streams at once races on that scratch.
  *    Use one context per concurrent stream; device keys may be shared.
- *    Growing the scratch frees the old buffer, which waits for the device.
+ *    Growing the scratch retires the old buffer instead of freeing it: it
+ *    stays allocated until fs_ctx_destroy, so work already enqueued, or
+ *    captured into a graph before the growth, still runs on valid memory
+ *    (and keeps using the old buffer when replayed).  fs_ctx_reserve before
+ *    a capture avoids growth altogether.
  *  - Only k = 1 (one mask polynomial per RLWE sample) is supported.
  */
 #ifndef FHESNN_H
@@ -185,6 +189,11 @@ FS_API int fs_ctx_destroy(fs_ctx* ctx);
  * stream capture into a graph). */
 FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
 
+/* Device bytes of the context's scratch: *live = the buffers in use now,
+ * *retired = buffers replaced by larger ones, held until fs_ctx_destroy
+ * (see the conventions above).  Either pointer may be NULL. */
+FS_API int fs_ctx_scratch_bytes(const fs_ctx* ctx, size_t* live, size_t* retired);
+
 /* Tuning of the blind-rotation kernel.  Every variant computes the same
  * bits; they differ in when the key slice of a digit row is requested
  * (before or after its forward transform) and in the register budget the
@@ -195,29 +204,29 @@ FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
 FS_API int fs_br_variants(uint32_t N);
 FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
 
-/* Batches of at most max_jobs bootstrapping jobs (ciphertexts x program
- * functions) run each job on two groups of N/16 threads that split the
- * accumulator's two polynomials and exchange partial products once per CMux
- * step (same results; lower latency when the batch cannot fill the device).
- * Default: 3 x the device's compute units.  0 disables the split.  The
- * previous threshold is stored in *previous unless it is NULL. */
-FS_API int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous);
-
-/* Batches of at most max_jobs jobs (checked first) run each job on 2l
- * groups, one per digit row of the external product (Sec. 2.1, RGSW
- * product): a CMux step's critical path is one forward and one inverse
- * transform, for the lowest latency of a single bootstrapping or a few.
- * Same results.  Default: the device's compute units.  0 disables it.
- * *previous as above.  The thresholds are for N = 1024; at N = 2048 the
- * split one counts a third (measured crossovers of the wider jobs). */
-FS_API int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous);
-
-/* Batches of at most max_jobs jobs (checked after the row threshold and
- * before the split one; N = 1024 only) run the two-group form with two
- * jobs per workgroup, so that every SIMD of a CU holds one wave.  Same
- * results.  Default: 2 x the device's compute units.  0 disables it.
- * *previous as above. */
-FS_API int fs_ctx_set_paired(fs_ctx* ctx, size_t max_jobs, size_t* previous);
+/* Thread-group form of the blind rotation by batch size, per ring degree N
+ * (1024 or 2048; else FS_ENOTSUP).  A launch of B jobs (ciphertexts x
+ * program functions) takes the first form whose threshold it does not
+ * exceed, in this order; every form computes the same bits:
+ *  - rows (fs_ctx_set_rows): 2l groups of N/16 threads per job, one per
+ *    digit row of the external product (Sec. 2.1, RGSW product), so a CMux
+ *    step's critical path is one forward and one inverse transform: the
+ *    lowest latency for one bootstrapping or a few.  Default: the device's
+ *    compute units.
+ *  - paired (fs_ctx_set_paired, N = 1024 only): the two-group form below
+ *    with two jobs per workgroup, so that every SIMD of a CU holds one
+ *    wave.  Default: 2 x the compute units at N = 1024, 0 at N = 2048.
+ *  - split (fs_ctx_set_split): two groups of N/16 threads per job that split
+ *    the accumulator's two polynomials and exchange partial products once
+ *    per CMux step.  Default: 3 x the compute units at N = 1024, 0 at
+ *    N = 2048.
+ *  - otherwise one group per job (full batches).
+ * 0 disables a form.  The thresholds of one ring degree leave the other's
+ * unchanged.  The previous threshold is stored in *previous unless it is
+ * NULL.  The autotuner derives them from timings of every form. */
+FS_API int fs_ctx_set_rows(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous);
+FS_API int fs_ctx_set_paired(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous);
+FS_API int fs_ctx_set_split(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous);
 
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
  * the exact negacyclic transform on the device; the KSK is copied as is.
@@ -232,14 +241,17 @@ FS_API void fs_devkey_free(fs_devkey* dk);
  * y[o] = add[o] + sum_i W[o][i] * x[i], word by word mod 2^32.
  * W: dev int32 [O][I]; x: dev [I][dim]; add: dev [O][dim] or NULL;
  * y: dev [O][dim]; y == add is allowed (in-place accumulate), y must not
- * overlap x.  dim = ciphertext width (n+1). */
+ * overlap x.  dim = ciphertext width: n+1 under s, or N+1 for the
+ * ciphertexts under z that the key-switch-first order keeps between
+ * bootstrappings (fs_pbs_lif_ks_first), hence an argument. */
 FS_API int fs_lwe_linear(fs_ctx* ctx, const int32_t* W, size_t O, size_t I, uint32_t dim,
                   const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream);
 
 /* WeightSum of a 2-D convolution over ciphertext feature maps (Sec. 4.1):
  * x: dev [Ci][H][Wd][dim]; W: dev int32 [Co][Ci][K][K];
  * y: dev [Co][Ho][Wo][dim], Ho = (H + 2 pad - K)/stride + 1 (same for Wo);
- * taps falling in the zero padding contribute nothing.  add as above. */
+ * taps falling in the zero padding contribute nothing.  add and dim as
+ * above. */
 FS_API int fs_lwe_conv2d(fs_ctx* ctx, const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd,
                   uint32_t Co, uint32_t K, uint32_t stride, uint32_t pad, uint32_t dim,
                   const uint32_t* x, const uint32_t* add, uint32_t* y, void* stream);
@@ -326,7 +338,9 @@ typedef struct fs_lif_range {
  * device; ranges of one key are key-switched together.  ranges: host
  * [nranges].  The context's scratch and range table are reused by the next
  * call: calls on one context must not overlap (use one context per
- * stream). */
+ * stream).  The range table is copied from host memory at the call, so the
+ * call cannot be captured into a graph: on a capturing stream it returns
+ * FS_ENOTSUP. */
 FS_API int fs_pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges,
                              size_t nranges, void* stream);
 
@@ -337,7 +351,8 @@ FS_API int fs_pbs_lif_ranges_many_lut(fs_ctx* ctx, const fs_lif* lif, const fs_l
                                       size_t nranges, void* stream);
 
 /* Key switching z -> s alone (Sec. 2.1, Key Switching step).
- * in: dev [B][N+1] under z; out: dev [B][n+1] under s. */
+ * in: dev [B][N+1] under z; out: dev [B][n+1] under s; the key must live
+ * on the context's device (else FS_EPARAM). */
 FS_API int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,
                  void* stream);
 

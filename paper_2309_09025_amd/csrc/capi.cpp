@@ -31,11 +31,25 @@ struct fs_devkey {
   size_t bytes = 0;
 };
 
+// Batch-size thresholds of the thread-group forms for one ring degree (see
+// br_groups): up to `rows` jobs one group per digit row, then up to `paired`
+// two-group jobs in pairs (N = 1024 only), then up to `split` two groups per
+// job, then one group.
+struct GroupLimits {
+  size_t rows = 0, paired = 0, split = 0;
+};
+
 struct fs_ctx {
   int device = 0;
+  int cus = 0;  // compute units of the device
   std::mutex mu;
   uint32_t* ext = nullptr;  // extracted samples between blind rotation and key switch
   size_t ext_words = 0;
+  // Scratch buffers replaced by larger ones.  They stay allocated until
+  // fs_ctx_destroy: work captured into a graph before the growth holds
+  // their addresses in its kernel arguments and still runs on them.
+  std::vector<void*> retired;
+  size_t retired_bytes = 0;
   // test polynomials on the device, keyed by (N, p, residue table)
   std::map<std::vector<int32_t>, uint32_t*> tpoly;
   // NTT tables per ring degree for fs_ntt_polymul
@@ -43,12 +57,8 @@ struct fs_ctx {
   std::map<uint32_t, fs::UniTw> table_uni;
   // blind-rotation kernel variant per ring degree (chosen by the tuner)
   std::map<uint32_t, int> br_variant;
-  // batches up to this many jobs run each job on two polynomial groups
-  // (set at creation to 4 x the device's compute units: below that the
-  // one-group kernel leaves SIMDs idle)
-  size_t split_max_jobs = 0;
-  size_t rows_max_jobs = 0;    // batches up to this size: one thread group per digit row
-  size_t paired_max_jobs = 0;  // then up to this size: two-group jobs in pairs (N = 1024)
+  // thread-group thresholds per ring degree (defaults: default_limits)
+  std::map<uint32_t, GroupLimits> limits;
   // device copy of the range table of the last multi-key launch
   fs::JobRange* ranges = nullptr;
   size_t ranges_cap = 0;
@@ -175,14 +185,52 @@ int check_params(const fs_params* p) {
   return FS_OK;
 }
 
+// Grow the extracted-sample scratch to at least `words`.  The old buffer is
+// retired, not freed (a captured graph may still use it), and the new one
+// is half as large again as the old at least, so the retired buffers of a
+// context never add up to more than twice its live scratch.
 int ensure_ext(fs_ctx* ctx, size_t words) {
   if (ctx->ext_words >= words) return FS_OK;
-  if (ctx->ext) FS_HIP(hipFree(ctx->ext));
-  ctx->ext = nullptr;
-  ctx->ext_words = 0;
-  FS_HIP(hipMalloc(&ctx->ext, words * sizeof(uint32_t)));
+  const size_t grown = std::max(words, ctx->ext_words + ctx->ext_words / 2);
+  uint32_t* fresh = nullptr;
+  hipError_t e = hipMalloc(&fresh, grown * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    e = hipMalloc(&fresh, words * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(FS_ENOMEM, "scratch allocation failed");
+  } else {
+    words = grown;
+  }
+  if (ctx->ext) {
+    ctx->retired.push_back(ctx->ext);
+    ctx->retired_bytes += ctx->ext_words * sizeof(uint32_t);
+  }
+  ctx->ext = fresh;
   ctx->ext_words = words;
   return FS_OK;
+}
+
+// Thresholds of the thread-group forms for ring degree N on this context:
+// the tuned ones if set, else the measured defaults.  N = 1024: one job per
+// CU on the row kernel, then two-group jobs in pairs up to 2 x CUs, then
+// two groups up to 3 x CUs, then one group.  N = 2048: the row kernel holds
+// one job per CU (148 KiB of LDS), there is no paired form and two groups
+// measured no faster than one beyond the row kernel's range.
+GroupLimits limits_for(const fs_ctx* ctx, uint32_t N) {
+  auto it = ctx->limits.find(N);
+  if (it != ctx->limits.end()) return it->second;
+  GroupLimits g;
+  g.rows = (size_t)ctx->cus;
+  if (N == 1024) {
+    g.paired = 2 * (size_t)ctx->cus;
+    g.split = 3 * (size_t)ctx->cus;
+  }
+  return g;
+}
+
+// A stream that is being captured into a graph.
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
 // device test polynomial of a residue table f: Z_p -> Z_p_out (p_out = 0:
@@ -242,18 +290,13 @@ int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const 
   return FS_OK;
 }
 
-// thread groups per job for a batch of this size (see launch_blind_rotate).
-// The thresholds are set for N = 1024: one job per CU on the row kernel,
-// then two-group jobs in pairs (one wave per SIMD), then two-group jobs,
-// then one group.  At N = 2048 the row kernel holds one job per CU (148 KiB
-// of LDS), there is no paired form, and the two-group kernel measured no
-// faster than one group beyond the row kernel's range, hence a third of the
-// split threshold.
+// thread groups per job for a batch of this size (see launch_blind_rotate),
+// from the context's thresholds for ring degree N, checked in order
 int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs) {
-  if (jobs <= ctx->rows_max_jobs) return kBrRows;
-  if (N == 2048) return jobs <= ctx->split_max_jobs / 3 ? kBrTwo : kBrOne;
-  if (jobs <= ctx->paired_max_jobs) return kBrTwoPaired;
-  return jobs <= ctx->split_max_jobs ? kBrTwo : kBrOne;
+  const GroupLimits g = limits_for(ctx, N);
+  if (jobs <= g.rows) return kBrRows;
+  if (N == 1024 && jobs <= g.paired) return kBrTwoPaired;
+  return jobs <= g.split ? kBrTwo : kBrOne;
 }
 
 // blind rotation of jobs = B * nlut, then key switch (or not)
@@ -339,6 +382,10 @@ int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, s
   std::lock_guard<std::mutex> lk(ctx->mu);
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
+  // the range table is copied from host memory that the next call rewrites:
+  // a graph replaying that copy would read another call's ranges
+  if (capturing(st))
+    return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: cannot be captured into a graph");
   uint32_t* tp[2] = {nullptr, nullptr};
   if (many) {
     rc = get_tpoly_two(ctx, P.N, P.p, fire.data(), reset.data(), &tp[0]);
@@ -358,11 +405,15 @@ int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, s
   }
   if (total > 0x3FFFFFFFull) return fail(FS_EINVAL, "fs_pbs_lif_ranges: batch too large");
   if (ctx->ranges_cap < host.size()) {
-    if (ctx->ranges) FS_HIP(hipFree(ctx->ranges));
-    ctx->ranges = nullptr;
-    ctx->ranges_cap = 0;
-    FS_HIP(hipMalloc(&ctx->ranges, host.size() * sizeof(JobRange)));
-    ctx->ranges_cap = host.size();
+    const size_t cap = std::max(host.size(), 2 * ctx->ranges_cap);
+    JobRange* fresh = nullptr;
+    FS_HIP(hipMalloc(&fresh, cap * sizeof(JobRange)));
+    if (ctx->ranges) {  // retired like the sample scratch
+      ctx->retired.push_back(ctx->ranges);
+      ctx->retired_bytes += ctx->ranges_cap * sizeof(JobRange);
+    }
+    ctx->ranges = fresh;
+    ctx->ranges_cap = cap;
   }
   FS_HIP(hipMemcpyAsync(ctx->ranges, host.data(), host.size() * sizeof(JobRange),
                         hipMemcpyHostToDevice, st));
@@ -577,11 +628,7 @@ int fs_ctx_create(int device, fs_ctx** ctx) {
   FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   auto* c = new fs_ctx;
   c->device = device;
-  // measured crossovers (4096 bootstrappings' worth of kernels, N = 1024):
-  // one group per digit row wins up to 2 jobs per CU, two groups up to 3
-  c->split_max_jobs = 3 * (size_t)cus;
-  c->rows_max_jobs = (size_t)cus;
-  c->paired_max_jobs = 2 * (size_t)cus;
+  c->cus = cus;  // the thread-group thresholds default to multiples of it
   *ctx = c;
   return FS_OK;
 }
@@ -592,6 +639,7 @@ int fs_ctx_destroy(fs_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->ext) (void)hipFree(ctx->ext);
   if (ctx->ranges) (void)hipFree(ctx->ranges);
+  for (void* p : ctx->retired) (void)hipFree(p);
   for (auto& kv : ctx->tpoly) (void)hipFree(kv.second);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   delete ctx;
@@ -606,30 +654,38 @@ int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs) {
   return ensure_ext(ctx, max_jobs * (size_t)(N + 1));
 }
 
+int fs_ctx_scratch_bytes(const fs_ctx* ctx, size_t* live, size_t* retired) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  if (live) *live = ctx->ext_words * sizeof(uint32_t) + ctx->ranges_cap * sizeof(JobRange);
+  if (retired) *retired = ctx->retired_bytes;
+  return FS_OK;
+}
+
 int fs_br_variants(uint32_t N) { return blind_rotate_variants(N); }
 
-int fs_ctx_set_split(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
+// one threshold of ring degree N: which = 0 rows, 1 paired, 2 split
+static int set_limit(fs_ctx* ctx, uint32_t N, int which, size_t max_jobs, size_t* previous) {
   if (!ctx) return fail(FS_EINVAL, "null context");
+  if (N != 1024 && N != 2048) return fail(FS_ENOTSUP, "ring degree without kernels");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (previous) *previous = ctx->split_max_jobs;
-  ctx->split_max_jobs = max_jobs;
+  GroupLimits g = limits_for(ctx, N);
+  size_t& v = which == 0 ? g.rows : which == 1 ? g.paired : g.split;
+  if (previous) *previous = v;
+  v = max_jobs;
+  ctx->limits[N] = g;
   return FS_OK;
 }
 
-int fs_ctx_set_rows(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
-  if (!ctx) return fail(FS_EINVAL, "null context");
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  if (previous) *previous = ctx->rows_max_jobs;
-  ctx->rows_max_jobs = max_jobs;
-  return FS_OK;
+int fs_ctx_set_rows(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous) {
+  return set_limit(ctx, N, 0, max_jobs, previous);
 }
 
-int fs_ctx_set_paired(fs_ctx* ctx, size_t max_jobs, size_t* previous) {
-  if (!ctx) return fail(FS_EINVAL, "null context");
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  if (previous) *previous = ctx->paired_max_jobs;
-  ctx->paired_max_jobs = max_jobs;
-  return FS_OK;
+int fs_ctx_set_paired(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous) {
+  return set_limit(ctx, N, 1, max_jobs, previous);
+}
+
+int fs_ctx_set_split(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous) {
+  return set_limit(ctx, N, 2, max_jobs, previous);
 }
 
 int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant) {
@@ -935,6 +991,7 @@ int fs_pbs_lif_ranges_many_lut(fs_ctx* ctx, const fs_lif* lif, const fs_lif_rang
 int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, size_t B, uint32_t* out,
                  void* stream) {
   if (!ctx || !dk || (B && (!in || !out))) return fail(FS_EINVAL, "fs_keyswitch: null argument");
+  if (dk->device != ctx->device) return fail(FS_EPARAM, "fs_keyswitch: key lives on another device");
   if (B > 0x7FFFFFFFull) return fail(FS_EINVAL, "fs_keyswitch: batch too large");
   DeviceGuard g(ctx->device);
   const fs_params& P = dk->prm;

@@ -68,9 +68,10 @@ SIGNATURES = {
     "fs_encrypt_z": (_int, [_vp, _i32p, _sz, _u64, _u64, _u32p]),
     "fs_decrypt": (_int, [_vp, _u32p, _sz, _u32, _i32p]),
     "fs_secret_export": (_int, [_vp, _i32p, _i32p]),
-    "fs_ctx_set_split": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
-    "fs_ctx_set_rows": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
-    "fs_ctx_set_paired": (_int, [_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "fs_ctx_set_split": (_int, [_vp, _u32, _sz, ctypes.POINTER(_sz)]),
+    "fs_ctx_set_rows": (_int, [_vp, _u32, _sz, ctypes.POINTER(_sz)]),
+    "fs_ctx_set_paired": (_int, [_vp, _u32, _sz, ctypes.POINTER(_sz)]),
+    "fs_ctx_scratch_bytes": (_int, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "fs_evk_export": (_int, [_vp, _u32p, _u32p]),
     "fs_evk_params": (_int, [_vp, _PP]),
     "fs_secret_free": (None, [_vp]),
@@ -141,11 +142,28 @@ def _np_i32(a):
 
 
 def _dptr(t):
-    """Device pointer of a torch tensor (None -> NULL)."""
+    """Device pointer of a contiguous int32 device tensor (None -> NULL).
+    The library cannot see buffer sizes, so every caller checks shapes
+    first; this checks placement and element type."""
     if t is None:
         return None
-    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if t.dtype != torch.int32:
+        raise ValueError(f"expected an int32 tensor, got {t.dtype}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _rows(fn: str, name: str, t, rows: int, width: int):
+    """Raise unless t is a 2-D [rows][width] tensor."""
+    if t is None or t.dim() != 2 or t.shape[0] != rows or t.shape[1] != width:
+        got = None if t is None else tuple(t.shape)
+        raise ValueError(f"{fn}: {name} must be [{rows}][{width}], got {got}")
 
 
 def _stream(stream):
@@ -301,32 +319,39 @@ class Context:
     def reserve(self, N: int, max_jobs: int):
         _check("fs_ctx_reserve", lib().fs_ctx_reserve(self.h, N, max_jobs))
 
-    def set_split(self, max_jobs: int) -> int:
-        """Batches of at most max_jobs jobs use two thread groups per job;
-        returns the previous threshold."""
+    def _set_limit(self, fn: str, N: int, max_jobs: int) -> int:
         prev = ctypes.c_size_t()
-        _check("fs_ctx_set_split", lib().fs_ctx_set_split(self.h, max_jobs, ctypes.byref(prev)))
+        _check(fn, getattr(lib(), fn)(self.h, N, max_jobs, ctypes.byref(prev)))
         return prev.value
 
-    def set_rows(self, max_jobs: int) -> int:
-        """Batches of at most max_jobs jobs use one thread group per digit
-        row (lowest latency); returns the previous threshold."""
-        prev = ctypes.c_size_t()
-        _check("fs_ctx_set_rows", lib().fs_ctx_set_rows(self.h, max_jobs, ctypes.byref(prev)))
-        return prev.value
+    def set_split(self, N: int, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs at ring degree N use two thread
+        groups per job; returns the previous threshold."""
+        return self._set_limit("fs_ctx_set_split", N, max_jobs)
 
-    def set_paired(self, max_jobs: int) -> int:
-        """Batches of at most max_jobs jobs (after the row threshold) use two
-        thread groups per job and two jobs per workgroup (N = 1024); returns
-        the previous threshold."""
-        prev = ctypes.c_size_t()
-        _check("fs_ctx_set_paired", lib().fs_ctx_set_paired(self.h, max_jobs, ctypes.byref(prev)))
-        return prev.value
+    def set_rows(self, N: int, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs at ring degree N use one thread
+        group per digit row (lowest latency); returns the previous threshold."""
+        return self._set_limit("fs_ctx_set_rows", N, max_jobs)
 
-    def groups(self, mode: str):
-        """Context manager forcing the thread groups per job: "one", "two",
-        "paired" (two groups, two jobs per workgroup; N = 1024) or "rows"
-        (restores the thresholds on exit)."""
+    def set_paired(self, N: int, max_jobs: int) -> int:
+        """Batches of at most max_jobs jobs at ring degree N (after the row
+        threshold) use two thread groups per job and two jobs per workgroup
+        (N = 1024 only); returns the previous threshold."""
+        return self._set_limit("fs_ctx_set_paired", N, max_jobs)
+
+    def scratch_bytes(self):
+        """(live, retired) device bytes of the context's scratch."""
+        live, retired = ctypes.c_size_t(), ctypes.c_size_t()
+        _check("fs_ctx_scratch_bytes", lib().fs_ctx_scratch_bytes(self.h, ctypes.byref(live),
+                                                                  ctypes.byref(retired)))
+        return live.value, retired.value
+
+    def groups(self, mode: str, N=None):
+        """Context manager forcing the thread groups per job at ring degree N
+        (None: both 1024 and 2048): "one", "two", "paired" (two groups, two
+        jobs per workgroup; N = 1024) or "rows" (restores the thresholds on
+        exit)."""
         import contextlib
 
         @contextlib.contextmanager
@@ -334,13 +359,17 @@ class Context:
             big = 1 << 40
             rows, paired, split = {"one": (0, 0, 0), "two": (0, 0, big), "paired": (0, big, 0),
                                    "rows": (big, 0, 0)}[mode]
-            pr, pp, ps = self.set_rows(rows), self.set_paired(paired), self.set_split(split)
+            saved = []
+            for n in ((1024, 2048) if N is None else (N,)):
+                saved.append((n, self.set_rows(n, rows), self.set_paired(n, paired),
+                              self.set_split(n, split)))
             try:
                 yield self
             finally:
-                self.set_rows(pr)
-                self.set_paired(pp)
-                self.set_split(ps)
+                for n, pr, pp, ps in saved:
+                    self.set_rows(n, pr)
+                    self.set_paired(n, pp)
+                    self.set_split(n, ps)
         return cm()
 
     def set_br_variant(self, N: int, variant: int):
@@ -375,30 +404,65 @@ def evk_upload(ctx: Context, evk: EvalKey) -> DevKey:
 
 
 def lwe_linear(ctx: Context, W, x, y, add=None, stream=None):
+    """y = add + W x on ciphertext rows: W [O][I], x [I][dim], y and add
+    [O][dim]."""
+    if W.dim() != 2 or x.dim() != 2:
+        raise ValueError("lwe_linear: W must be [O][I] and x [I][dim]")
     O, I = W.shape
-    _check("fs_lwe_linear", lib().fs_lwe_linear(ctx.h, _dptr(W), O, I, x.shape[1], _dptr(x),
+    dim = x.shape[1]
+    _rows("lwe_linear", "x", x, I, dim)
+    _rows("lwe_linear", "y", y, O, dim)
+    if add is not None:
+        _rows("lwe_linear", "add", add, O, dim)
+    _check("fs_lwe_linear", lib().fs_lwe_linear(ctx.h, _dptr(W), O, I, dim, _dptr(x),
                                                 _dptr(add), _dptr(y), _stream(stream)))
     return y
 
 
+def conv_out_size(H: int, Wd: int, K: int, stride: int, pad: int):
+    """(Ho, Wo) of a K x K convolution with this stride and zero padding."""
+    return (H + 2 * pad - K) // stride + 1, (Wd + 2 * pad - K) // stride + 1
+
+
 def lwe_conv2d(ctx: Context, W, x, y, Ci, H, Wd, stride, pad, add=None, stream=None):
+    """Convolution WeightSum: W [Co][Ci][K][K], x [Ci*H*Wd][dim], y and add
+    [Co*Ho*Wo][dim]."""
+    if W.dim() != 4 or W.shape[1] != Ci or W.shape[2] != W.shape[3]:
+        raise ValueError(f"lwe_conv2d: W must be [Co][{Ci}][K][K]")
     Co, _, K, _ = W.shape
+    if x.dim() != 2:
+        raise ValueError("lwe_conv2d: x must be [Ci*H*Wd][dim]")
+    dim = x.shape[1]
+    _rows("lwe_conv2d", "x", x, Ci * H * Wd, dim)
+    if stride > 0 and H + 2 * pad >= K and Wd + 2 * pad >= K:  # else the library rejects it
+        Ho, Wo = conv_out_size(H, Wd, K, stride, pad)
+        _rows("lwe_conv2d", "y", y, Co * Ho * Wo, dim)
+        if add is not None:
+            _rows("lwe_conv2d", "add", add, Co * Ho * Wo, dim)
     _check("fs_lwe_conv2d", lib().fs_lwe_conv2d(ctx.h, _dptr(W), Ci, H, Wd, Co, K, stride, pad,
-                                                x.shape[-1], _dptr(x), _dptr(add), _dptr(y),
+                                                dim, _dptr(x), _dptr(add), _dptr(y),
                                                 _stream(stream)))
     return y
 
 
 def lwe_add(ctx: Context, a, b, y, stream=None):
+    """y = a + b word by word; a, b, y of one shape."""
+    if tuple(b.shape) != tuple(a.shape) or tuple(y.shape) != tuple(a.shape):
+        raise ValueError(f"lwe_add: a, b and y must have one shape, got {tuple(a.shape)}, "
+                         f"{tuple(b.shape)}, {tuple(y.shape)}")
     _check("fs_lwe_add", lib().fs_lwe_add(ctx.h, _dptr(a), _dptr(b), a.numel(), _dptr(y),
                                           _stream(stream)))
     return y
 
 
 def lwe_add_plain(ctx: Context, p: int, x, c, y, stream=None):
-    """y = x + Delta c on the body word of each row; c: device int32 [rows]."""
-    import torch
-    assert c.dtype == torch.int32 and c.numel() == x.shape[0]
+    """y = x + Delta c on the body word of each row; x, y [rows][dim],
+    c: device int32 [rows]."""
+    if x.dim() != 2:
+        raise ValueError("lwe_add_plain: x must be [rows][dim]")
+    _rows("lwe_add_plain", "y", y, x.shape[0], x.shape[1])
+    if c.dim() != 1 or c.numel() != x.shape[0]:
+        raise ValueError(f"lwe_add_plain: c must be [{x.shape[0]}]")
     _check("fs_lwe_add_plain", lib().fs_lwe_add_plain(ctx.h, p, _dptr(x), _dptr(c), x.shape[0],
                                                       x.shape[1], _dptr(y), _stream(stream)))
     return y
@@ -437,6 +501,12 @@ def pbs_mspace(ctx: Context, dk: DevKey, lut, p_in: int, p_out: int, x, out,
 
 
 def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out, stream=None):
+    """One LIF activation: h, spike2_out, v_out are [B][n+1]."""
+    w = dk.params.n + 1
+    if h.dim() != 2:
+        raise ValueError(f"pbs_lif: h must be [B][{w}]")
+    for name, t in (("h", h), ("spike2_out", spike2_out), ("v_out", v_out)):
+        _rows("pbs_lif", name, t, h.shape[0], w)
     lif = CLif(v_th, tau)
     _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
                                           _dptr(spike2_out), _dptr(v_out), _stream(stream)))
@@ -488,13 +558,26 @@ def pbs_lif_ranges(ctx: Context, v_th: int, tau: int, ranges, stream=None,
 
 
 def keyswitch(ctx: Context, dk: DevKey, x, out, stream=None):
+    """x [B][N+1] under z -> out [B][n+1] under s."""
+    P = dk.params
+    if x.dim() != 2:
+        raise ValueError(f"keyswitch: x must be [B][{P.N + 1}]")
+    _rows("keyswitch", "x", x, x.shape[0], P.N + 1)
+    _rows("keyswitch", "out", out, x.shape[0], P.n + 1)
     _check("fs_keyswitch", lib().fs_keyswitch(ctx.h, dk.h, _dptr(x), x.shape[0], _dptr(out),
                                               _stream(stream)))
     return out
 
 
 def ntt_polymul(ctx: Context, N: int, dmax: int, d, b, out, stream=None):
+    """out = sum_r d_r b_r mod X^N + 1: d, b [R][N], out [N]."""
+    if d.dim() != 2:
+        raise ValueError(f"ntt_polymul: d must be [R][{N}]")
     R = d.shape[0]
+    _rows("ntt_polymul", "d", d, R, N)
+    _rows("ntt_polymul", "b", b, R, N)
+    if out.dim() != 1 or out.shape[0] != N:
+        raise ValueError(f"ntt_polymul: out must be [{N}]")
     _check("fs_ntt_polymul", lib().fs_ntt_polymul(ctx.h, N, R, dmax, _dptr(d), _dptr(b),
                                                   _dptr(out), _stream(stream)))
     return out

@@ -145,7 +145,7 @@ def tune_groups(ctx: F.Context, dk: F.DevKey, intervals: int = 4, reps: int = 2,
             ext = F.empty_ct(jobs, P.N + 1)
             times[jobs] = {}
             for form in forms:
-                with ctx.groups(form):
+                with ctx.groups(form, P.N):
                     F.pbs(ctx, dk, lut, x, ext, keyswitch=False, stream=stream)  # warm
                     torch.cuda.synchronize()
                     e0 = torch.cuda.Event(enable_timing=True)
@@ -162,9 +162,7 @@ def tune_groups(ctx: F.Context, dk: F.DevKey, intervals: int = 4, reps: int = 2,
             cache[key] = {"best": best, "ms": {str(j): v for j, v in times.items()}}
             _store(cache)
     rows, paired, split = thresholds_from_best(best, cus)
-    if P.N == 2048:  # the library counts a third of the split threshold there
-        split *= 3
-    ctx.set_rows(rows)
-    ctx.set_paired(paired)
-    ctx.set_split(split)
+    ctx.set_rows(P.N, rows)  # this ring degree's only: the other keeps its own
+    ctx.set_paired(P.N, paired)
+    ctx.set_split(P.N, split)
     return (rows, paired, split), times

@@ -194,7 +194,8 @@ _CTX_ENTRY_POINTS = ["fs_lwe_linear", "fs_lwe_conv2d", "fs_lwe_add", "fs_lwe_add
                      "fs_pbs", "fs_pbs_lif", "fs_pbs_mspace", "fs_pbs_lif_many_lut",
                      "fs_pbs_lif_ks_first", "fs_pbs_lif_ranges", "fs_pbs_lif_ranges_many_lut",
                      "fs_keyswitch", "fs_ntt_polymul", "fs_evk_upload", "fs_ctx_set_br_variant",
-                     "fs_ctx_set_split", "fs_ctx_set_rows", "fs_ctx_set_paired", "fs_ctx_reserve"]
+                     "fs_ctx_set_split", "fs_ctx_set_rows", "fs_ctx_set_paired", "fs_ctx_reserve",
+                     "fs_ctx_scratch_bytes"]
 
 
 @pytest.mark.parametrize("name", _CTX_ENTRY_POINTS)
