@@ -229,9 +229,12 @@ FS_API int fs_ctx_set_paired(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* p
 FS_API int fs_ctx_set_split(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* previous);
 
 /* Upload an evaluation key to HBM: the BSK is moved to the NTT domain of
- * the exact negacyclic transform on the device; the KSK is copied as is.
- * Synchronous.  The device key is immutable afterwards and may be shared
- * by calls on any stream of the context's device. */
+ * the exact negacyclic transform on the device; the KSK is kept as signed
+ * byte planes for the matrix-core key switch when its digits are t = 8 of
+ * base 4 (the word form is then freed after the conversion), else copied
+ * as is.  fs_devkey_bytes reports what stays resident.  Synchronous.  The
+ * device key is immutable afterwards and may be shared by calls on any
+ * stream of the context's device. */
 FS_API int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk);
 FS_API int fs_devkey_params(const fs_devkey* dk, fs_params* out);
 FS_API size_t fs_devkey_bytes(const fs_devkey* dk);
@@ -365,6 +368,26 @@ FS_API int fs_keyswitch(fs_ctx* ctx, const fs_devkey* dk, const uint32_t* in, si
  * 16-bit halves internally, as the blind rotation does). */
 FS_API int fs_ntt_polymul(fs_ctx* ctx, uint32_t N, uint32_t R, int32_t dmax, const int32_t* d,
                    const uint32_t* b, uint32_t* out, void* stream);
+
+/* ---------------------------------------------------------- measurement */
+
+/* Issue-rate ceiling of the binary64 vector ALU, which bounds the blind
+ * rotation (its exact modular arithmetic; Sec. 2.1, RGSW product).  Runs
+ * one register-only kernel on `device` with exactly waves_per_simd (1..8)
+ * waves on every SIMD and stores the lane-instructions per second it
+ * issued (and the kernel time in *ms unless NULL).  kind 0: butterflies of
+ * the modular product (8 instructions each, the transforms' inner step);
+ * 1: modular multiply-accumulate (7, the pointwise products, plus one add
+ * that keeps its operand loop-carried); 2: bare fused multiply-add (1).  Allocates and frees its own small buffer;
+ * synchronous; the caller's current device is restored. */
+FS_API int fs_probe_valu(int device, uint32_t waves_per_simd, uint32_t kind,
+                         double* lane_instr_per_s, double* ms);
+
+/* HBM streaming ceiling: a device copy of bytes/2 into bytes/2 (bytes
+ * >= 1 MiB), timed over five launches; stores bytes moved per second (read
+ * plus written) and the time per copy in *ms unless NULL.  Allocates and
+ * frees its buffers; synchronous. */
+FS_API int fs_probe_hbm(int device, size_t bytes, double* bytes_per_s, double* ms);
 
 #ifdef __cplusplus
 }

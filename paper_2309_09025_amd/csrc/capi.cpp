@@ -22,8 +22,10 @@ struct fs_devkey {
   fs_params prm{};
   int device = 0;
   double* bsk = nullptr;    // NTT domain, see launch_bsk_to_ntt
-  uint32_t* ksk = nullptr;  // [N][t][base-1][n+1]
-  int8_t* kskp = nullptr;   // the KSK as byte planes for the matrix-core key switch
+  // the KSK: byte planes for the matrix-core key switch (t = 8, base 4),
+  // else [N][t][base-1][n+1] words for the generic kernel; the other is null
+  uint32_t* ksk = nullptr;
+  int8_t* kskp = nullptr;
   double* fwd_tw = nullptr;
   double* inv_tw = nullptr;
   double* post = nullptr;
@@ -709,40 +711,53 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   auto* dk = new fs_devkey;
   dk->prm = P;
   dk->device = ctx->device;
+  // The matrix-core key switch (t = 8 digits of base 4) reads the KSK only
+  // as byte planes, built on the device from a staging copy that is then
+  // freed; other digit shapes keep the uint32 key for the generic kernel.
+  const bool planes_form = P.ks_t == 8 && P.ks_base_bit == 2;
   uint32_t* coef = nullptr;
+  uint32_t* kstage = nullptr;
   auto cleanup = [&](int code) {
     if (coef) (void)hipFree(coef);
+    if (kstage) (void)hipFree(kstage);
     fs_devkey_free(dk);
     return code;
   };
   const size_t bsk_words = evk->bsk.size();
   const size_t bsk_ntt = bsk_words * limbs;  // doubles
+  const size_t ksk_bytes = evk->ksk.size() * sizeof(uint32_t);
   hipError_t e = hipMalloc(&dk->bsk, bsk_ntt * sizeof(double));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: BSK allocation failed"));
-  e = hipMalloc(&dk->ksk, evk->ksk.size() * sizeof(uint32_t));
+  uint32_t** ksk_dst = planes_form ? &kstage : &dk->ksk;
+  e = hipMalloc(ksk_dst, ksk_bytes);
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK allocation failed"));
-  const size_t planes = fs::ksk_planes_bytes(P.N, P.n);
-  e = hipMalloc(&dk->kskp, planes);
-  if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK plane allocation failed"));
+  const size_t planes = planes_form ? fs::ksk_planes_bytes(P.N, P.n) : 0;
+  if (planes_form) {
+    e = hipMalloc(&dk->kskp, planes);
+    if (e != hipSuccess)
+      return cleanup(fail(FS_ENOMEM, "fs_evk_upload: KSK plane allocation failed"));
+  }
   e = hipMalloc(&coef, bsk_words * sizeof(uint32_t));
   if (e != hipSuccess) return cleanup(fail(FS_ENOMEM, "fs_evk_upload: staging allocation failed"));
   rc = upload_tables(P.N, &dk->fwd_tw, &dk->inv_tw, &dk->post, &dk->uni);
   if (rc) return cleanup(rc);
   e = hipMemcpy(coef, evk->bsk.data(), bsk_words * sizeof(uint32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(dk->ksk, evk->ksk.data(), evk->ksk.size() * sizeof(uint32_t),
-                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(*ksk_dst, evk->ksk.data(), ksk_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: copy"));
   rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
                  "BSK conversion");
   if (rc) return cleanup(rc);
-  rc = launch_rc(launch_ksk_to_planes(P.N, P.n, dk->ksk, dk->kskp, nullptr), "KSK conversion");
-  if (rc) return cleanup(rc);
+  if (planes_form) {
+    rc = launch_rc(launch_ksk_to_planes(P.N, P.n, kstage, dk->kskp, nullptr), "KSK conversion");
+    if (rc) return cleanup(rc);
+  }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: conversion"));
   (void)hipFree(coef);
   coef = nullptr;
-  dk->bytes = bsk_ntt * sizeof(double) + evk->ksk.size() * sizeof(uint32_t) + planes +
+  if (kstage) (void)hipFree(kstage);
+  kstage = nullptr;
+  dk->bytes = bsk_ntt * sizeof(double) + (planes_form ? planes : ksk_bytes) +
               (size_t)(5 * P.N / 2) * sizeof(double);
   *dk_out = dk;
   return FS_OK;

@@ -104,6 +104,10 @@ SIGNATURES = {
     "fs_pbs_lif_ranges_many_lut": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
     "fs_keyswitch": (_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "fs_ntt_polymul": (_int, [_vp, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
+    "fs_probe_valu": (_int, [_int, _u32, _u32, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)]),
+    "fs_probe_hbm": (_int, [_int, _sz, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -584,6 +588,25 @@ def ntt_polymul(ctx: Context, N: int, dmax: int, d, b, out, stream=None):
 
 
 # ------------------------------------------------------------------ torch helpers
+
+def probe_valu(device: int, waves_per_simd: int, kind: int):
+    """(lane-instructions/s, ms) of the binary64 VALU probe: kind 0 modular
+    butterflies, 1 modular multiply-accumulates, 2 bare FMAs, at exactly
+    waves_per_simd waves on every SIMD."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check("fs_probe_valu", lib().fs_probe_valu(device, waves_per_simd, kind,
+                                                ctypes.byref(rate), ctypes.byref(ms)))
+    return rate.value, ms.value
+
+
+def probe_hbm(device: int, nbytes: int):
+    """(bytes/s, ms per copy) of a device copy moving nbytes (half read,
+    half written)."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check("fs_probe_hbm", lib().fs_probe_hbm(device, nbytes, ctypes.byref(rate),
+                                              ctypes.byref(ms)))
+    return rate.value, ms.value
+
 
 def to_device(a: np.ndarray, device="cuda"):
     """Host uint32/int32 array -> device int32 tensor holding the same bits."""
