@@ -287,6 +287,25 @@ FS_API int fs_pbs(fs_ctx* ctx, const fs_devkey* dk, const int32_t* lut, const ui
 FS_API int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h, size_t B,
                uint32_t* spike2_out, uint32_t* v_out, void* stream);
 
+/* fs_pbs_lif for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs and bits as fs_pbs_lif, but it calls no hipMalloc,
+ * hipFree or allocating library routine: the test polynomials and the
+ * extracted samples between the blind rotation and the key switch live in
+ * one static device array of the library (33.6 MB per GPU, reserved when the
+ * library's code is loaded on that GPU and held until the process ends),
+ * whose address fs_ctx_create looks up once per device.
+ * Limits: B <= 4096 neurons at N = 1024 and B <= 2048 at N = 2048
+ * (2 B (N+1) words of samples must fit 2 x 4096 x 1025), p <= 256; larger
+ * batches return FS_EINVAL before any work is enqueued.
+ * Every call on one GPU shares that GPU's array, whatever its context, and
+ * the array keeps the last call's contents: calls that overlap on one GPU
+ * (on two streams, or from two contexts) race and give wrong results.
+ * Order them on one stream or synchronise between them. */
+FS_API int fs_pbs_lif_noalloc(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif,
+                              const uint32_t* h, size_t B, uint32_t* spike2_out,
+                              uint32_t* v_out, void* stream);
+
 /* fs_pbs with a change of message space (test polynomial of
  * fs_test_poly_mspace): inputs carry messages of Z_p_in, outputs
  * LWE(f(m)) with Delta_out = 2^32/p_out, e.g. a larger p_out so that the

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfhesnn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["host_keys.cpp", "capi.cpp", "pbs.hip", "linear.hip", "ceiling.hip"]
+SOURCES = ["host_keys.cpp", "capi.cpp", "pbs.hip", "linear.hip", "noalloc.hip", "ceiling.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

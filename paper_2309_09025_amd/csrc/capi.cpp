@@ -302,9 +302,11 @@ int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs) {
 }
 
 // blind rotation of jobs = B * nlut, then key switch (or not)
+// (into `fixed_ext` instead of the context's scratch when it is set)
 int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nlut,
             const uint32_t* in, size_t B, uint32_t* out0, uint32_t* out1,
-            const uint32_t plain_add[2], int keyswitch, hipStream_t st) {
+            const uint32_t plain_add[2], int keyswitch, hipStream_t st,
+            uint32_t* fixed_ext = nullptr) {
   const fs_params& P = dk->prm;
   const size_t jobs = B * nlut;
   auto vit = ctx->br_variant.find(P.N);
@@ -320,7 +322,9 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   br.inv_tw = dk->inv_tw;
   br.post = dk->post;
   br.uni = dk->uni;
-  if (keyswitch) {
+  if (keyswitch && fixed_ext) {
+    br.ext = fixed_ext;
+  } else if (keyswitch) {
     int rc = ensure_ext(ctx, jobs * (size_t)(P.N + 1));
     if (rc) return rc;
     br.ext = ctx->ext;
@@ -628,6 +632,14 @@ int fs_ctx_create(int device, fs_ctx** ctx) {
   if (device < 0 || device >= count) return fail(FS_EINVAL, "no such HIP device");
   int cus = 0;
   FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  {
+    // this device's address of the static scratch of fs_pbs_lif_noalloc
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const int rc = noalloc_setup(device);
+    if (rc) return fail(FS_EDEVICE, std::string("static scratch lookup: ") +
+                                        hipGetErrorString((hipError_t)rc));
+  }
   auto* c = new fs_ctx;
   c->device = device;
   c->cus = cus;  // the thread-group thresholds default to multiples of it
@@ -874,6 +886,48 @@ int fs_pbs_lif(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32
   if (rc) return rc;
   const uint32_t add[2] = {delta_of(p), 0u};  // 2S = bootstrap_Fire + 1
   return run_pbs(ctx, dk, tp, 2, h, B, spike2_out, v_out, add, 1, as_stream(stream));
+}
+
+int fs_pbs_lif_noalloc(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h,
+                       size_t B, uint32_t* spike2_out, uint32_t* v_out, void* stream) {
+  if (!ctx || !dk || !lif || (B && (!h || !spike2_out || !v_out)))
+    return fail(FS_EINVAL, "fs_pbs_lif_noalloc: null argument");
+  if (dk->device != ctx->device)
+    return fail(FS_EPARAM, "fs_pbs_lif_noalloc: key lives on another device");
+  const fs_params& P = dk->prm;
+  if (P.p > kTpPairMaxP) return fail(FS_ENOTSUP, "fs_pbs_lif_noalloc: needs p <= 256");
+  if (B > kNoallocExtWords / (2 * (size_t)(P.N + 1)))
+    return fail(FS_EINVAL, "fs_pbs_lif_noalloc: batch exceeds the static scratch (" +
+                               std::to_string(kNoallocExtWords / (2 * (size_t)(P.N + 1))) +
+                               " neurons at N = " + std::to_string(P.N) + ")");
+  // residue tables on the stack: nothing on this path allocates
+  int32_t fire[kTpPairMaxP], reset[kTpPairMaxP];
+  int rc = fs_lif_luts(lif, P.p, fire, reset);
+  if (rc) return rc;
+  TpPair tp{};
+  tp.N = P.N;
+  tp.p = P.p;
+  tp.delta = delta_of(P.p);
+  for (uint32_t r = 0; r < P.p; ++r) {
+    tp.f[0][r] = (uint32_t)fire[r];
+    tp.f[1][r] = (uint32_t)reset[r];
+  }
+  for (int k = 0; k < 2; ++k)  // Theorem 2.1: f(r + p/2) = -f(r) mod p
+    for (uint32_t r = 0; r < P.p; ++r)
+      if (((tp.f[k][(r + P.p / 2) & (P.p - 1)] + tp.f[k][r]) & (P.p - 1)) != 0)
+        return fail(FS_EINVAL, "fs_pbs_lif_noalloc: program function is not negacyclic");
+  if (B == 0) return FS_OK;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  uint32_t* base = noalloc_scratch(ctx->device);
+  if (!base) return fail(FS_EDEVICE, "fs_pbs_lif_noalloc: static scratch not set up");
+  hipStream_t st = as_stream(stream);
+  rc = launch_rc(launch_tpoly_pair(tp, base, st), "test polynomials");
+  if (rc) return rc;
+  uint32_t* const tps[2] = {base, base + P.N};
+  const uint32_t add[2] = {delta_of(P.p), 0u};  // 2S = bootstrap_Fire + 1
+  return run_pbs(ctx, dk, tps, 2, h, B, spike2_out, v_out, add, 1, st, base + kNoallocTpWords);
 }
 
 int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, const uint32_t* h,

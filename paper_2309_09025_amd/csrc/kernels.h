@@ -97,6 +97,21 @@ int launch_polymul(uint32_t N, const int32_t* d, const uint32_t* b, uint32_t R, 
                    const double* tw, const double* itw, const double* post, const UniTw& uni,
                    hipStream_t st);
 
+// Static scratch of fs_pbs_lif_noalloc (noalloc.hip): two test polynomials
+// of up to 2048 words, then extracted samples for up to 4096 neurons at
+// N = 1024 (2 x 4096 x 1025 words; 2048 neurons at N = 2048).  33.6 MB
+// per device, held until the process ends.
+constexpr size_t kNoallocTpWords = 2 * 2048;
+constexpr size_t kNoallocExtWords = 2 * 4096 * 1025;
+constexpr uint32_t kTpPairMaxP = 256;
+struct TpPair {
+  uint32_t f[2][kTpPairMaxP];  // residues of functions 0 and 1 (first p used)
+  uint32_t N, p, delta;
+};
+int noalloc_setup(int device);
+uint32_t* noalloc_scratch(int device);
+int launch_tpoly_pair(const TpPair& a, uint32_t* dst, hipStream_t st);
+
 int launch_lwe_linear(const int32_t* W, size_t O, size_t I, uint32_t dim, const uint32_t* x,
                       const uint32_t* add, uint32_t* y, hipStream_t st);
 int launch_lwe_conv2d(const int32_t* W, uint32_t Ci, uint32_t H, uint32_t Wd, uint32_t Co,

@@ -98,6 +98,7 @@ SIGNATURES = {
     "fs_pbs": (_int, [_vp, _vp, _i32p, _vp, _sz, _vp, _int, _vp]),
     "fs_pbs_lif": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_mspace": (_int, [_vp, _vp, _i32p, _u32, _u32, _vp, _sz, _vp, _int, _vp]),
+    "fs_pbs_lif_noalloc": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_many_lut": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ks_first": (_int, [_vp, _vp, _LP, _vp, _sz, _vp, _vp, _vp]),
     "fs_pbs_lif_ranges": (_int, [_vp, _LP, ctypes.POINTER(CLifRange), _sz, _vp]),
@@ -514,6 +515,22 @@ def pbs_lif(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
     lif = CLif(v_th, tau)
     _check("fs_pbs_lif", lib().fs_pbs_lif(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
                                           _dptr(spike2_out), _dptr(v_out), _stream(stream)))
+
+
+def pbs_lif_noalloc(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
+                    stream=None):
+    """pbs_lif through the entry point that allocates nothing (static
+    device scratch; calls overlapping on one GPU race): h, spike2_out,
+    v_out are [B][n+1]."""
+    w = dk.params.n + 1
+    if h.dim() != 2:
+        raise ValueError(f"pbs_lif_noalloc: h must be [B][{w}]")
+    for name, t in (("h", h), ("spike2_out", spike2_out), ("v_out", v_out)):
+        _rows("pbs_lif_noalloc", name, t, h.shape[0], w)
+    lif = CLif(v_th, tau)
+    _check("fs_pbs_lif_noalloc",
+           lib().fs_pbs_lif_noalloc(ctx.h, dk.h, ctypes.byref(lif), _dptr(h), h.shape[0],
+                                    _dptr(spike2_out), _dptr(v_out), _stream(stream)))
 
 
 def pbs_lif_many_lut(ctx: Context, dk: DevKey, v_th: int, tau: int, h, spike2_out, v_out,
