@@ -158,17 +158,38 @@ __device__ __forceinline__ void poly_sync() {
   }
 }
 
-template <int LOGN, int LO_FROM, int LO_TO>
+// Orders one wavefront's own LDS accesses (compiler fence only).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exchange between two register mappings through LDS.  Default: barriers
+// before and after the reads.  LEAN (polynomials of several waves, for the
+// blind rotation's one-group job, whose callers place the remaining
+// barriers): with TP = 128 the thread bit 6 is exponent bit 10 in the
+// mappings of rounds B and C, so there each wave owns the LDS half of the
+// coefficients with that bit equal to its wave number and the B <-> C
+// exchanges stay inside the wave (compiler fences only); an A <-> B
+// exchange crosses waves and keeps the barrier between its writes and
+// reads, but not the one after the reads: the next access of another wave
+// to the slots read here comes after the next transform's entry barrier.
+template <int LOGN, int LO_FROM, int LO_TO, bool LEAN = false>
 __device__ __forceinline__ void exchange(double x[16], double* lds, int t) {
   constexpr int TP = (1 << LOGN) / 16;
+  static_assert(!LEAN || TP <= 64 || (TP == 128 && LOGN == 11), "lean schedule derived for TP = 128");
+  constexpr bool CROSS = LO_FROM == LOGN - 4 || LO_TO == LOGN - 4;  // into or out of round A
   double* wp = lds + slot_base<LOGN, LO_FROM>(t);
   const double* rp = lds + slot_base<LOGN, LO_TO>(t);
 #pragma unroll
   for (int r = 0; r < 16; ++r) wp[slot_reg<LO_FROM>(r)] = x[r];
-  poly_sync<TP>();
+  if constexpr (LEAN && !CROSS) wave_sync();
+  else poly_sync<TP>();
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = rp[slot_reg<LO_TO>(r)];
-  poly_sync<TP>();
+  if constexpr (LEAN && TP > 64) wave_sync();
+  else poly_sync<TP>();
 }
 
 template <int N>
@@ -334,9 +355,14 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
 // leading stages the caller has already applied (by table, |x| <= 1.5 P
 // after two).  The per-thread roots of rounds B and C are requested one
 // round ahead.
-template <int LOGN, int DONE = 0>
+//
+// LEAN: the exchange schedule of `exchange` for one-group blind-rotation
+// jobs; `entry` then places a workgroup barrier before the first LDS write
+// (needed unless the caller's last access to the buffer was a transform's
+// round-B/C half of its own wave, see exchange).
+template <int LOGN, int DONE = 0, bool LEAN = false>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
-                                            const Tab& tw, int t) {
+                                            const Tab& tw, int t, bool entry = true) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
@@ -344,13 +370,16 @@ __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const Uni
   double wb[R::FB];
   load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb, tw, t);
   fwd_roundA_uni<LOGN, LOGN - 1 - DONE>(x, u);
-  exchange<LOGN, S::LOA, S::LOB>(x, lds, t);
+  if constexpr (LEAN && S::TP > 64) {
+    if (entry) __syncthreads();
+  }
+  exchange<LOGN, S::LOA, S::LOB, LEAN>(x, lds, t);
   double wc[R::FC];
   load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);
   fwd_stages_reg<LOGN, S::LOB, BHI, BHI, BHI>(x, wb);  // fifth stage
   reduce16<S::N>(x);
   fwd_stages_reg<LOGN, S::LOB, BHI, BHI - 1, 4>(x, wb);
-  exchange<LOGN, S::LOB, 0>(x, lds, t);
+  exchange<LOGN, S::LOB, 0, LEAN>(x, lds, t);
   // stages 3 .. LOGN-9 complete the second segment of four
   fwd_stages_reg<LOGN, 0, 3, 3, LOGN - 9>(x, wc);
   reduce16<S::N>(x);
@@ -415,9 +444,11 @@ __device__ __forceinline__ void inv_roundC_uni(double x[16], const UniTw& u, int
 // psi^-j N^-1 and a reduction, giving the exact centred residue in round-A
 // mapping (thread t, register r: coefficient t + TP r).  The per-thread roots
 // of each round are requested one round ahead.
-template <int LOGN>
+// LEAN and `entry` as for ntt_fwd_reg.
+template <int LOGN, bool LEAN = false>
 __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const UniTw& u,
-                                            const Tab& itw, const Tab& post, int t) {
+                                            const Tab& itw, const Tab& post, int t,
+                                            bool entry = true) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B': stages 4..BHI, round A': BHI+1..LOGN-1
@@ -427,11 +458,14 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
   inv_roundC_uni<LOGN>(x, u, 0, 2);
   reduce16<S::N>(x);
   inv_roundC_uni<LOGN>(x, u, 3, 3);
-  exchange<LOGN, 0, S::LOB>(x, lds, t);
+  if constexpr (LEAN && S::TP > 64) {
+    if (entry) __syncthreads();
+  }
+  exchange<LOGN, 0, S::LOB, LEAN>(x, lds, t);
   double wa[R::IA];
   load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wa, itw, t);
   inv_stages_reg<LOGN, S::LOB, 4, 4, BHI>(x, wb);
-  exchange<LOGN, S::LOB, S::LOA>(x, lds, t);
+  exchange<LOGN, S::LOB, S::LOA, LEAN>(x, lds, t);
   double wp[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) wp[r] = post.at((uint32_t)t * 8u, (uint32_t)(S::TP * r) * 8u);

@@ -136,6 +136,11 @@ blind_rotate_kernel(BrArgs a) {
   static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
   __shared__ double lds_all[JPW * W][S::LDS_DOUBLES];
   __shared__ uint32_t acc_all[JPW][2][N];
+  // one-group jobs of several waves use the lean exchange schedule (see
+  // exchange): one workgroup barrier per cross-wave exchange and one on
+  // entry to a transform instead of two per exchange.  The split form keeps
+  // the default, its partial-sum swap reuses the exchange buffers.
+  constexpr bool LEAN = W == 1;
   // first two forward stages by table (digit_row_two_stages): their
   // operands are raw digits, so the products take only 2 HALF values per
   // root.  Used for small digit ranges (Bg = 2^7: 3 x 128 entries, which
@@ -279,7 +284,9 @@ blind_rotate_kernel(BrArgs a) {
           for (int r = 0; r < 16; ++r)
             xd[r] = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
         }
-        ntt_fwd_reg<LOGN, TAB1 ? 2 : 0>(xd, lds, a.uni, fwd_tw, t);
+        // entry barrier of the exchange buffer: not before a step's first
+        // transform (the previous step ended with one)
+        ntt_fwd_reg<LOGN, TAB1 ? 2 : 0, LEAN>(xd, lds, a.uni, fwd_tw, t, c != c0 || lv != 0);
         if constexpr (PF == 0 || PF == 3) {
 #pragma unroll
           for (int h = 0; h < 16 / KCH; ++h) {
@@ -321,7 +328,9 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int lb = 0; lb < LIMBS; ++lb) {
         double* y = c == 0 ? p0[lb] : p1[lb];
-        ntt_inv_reg<LOGN>(y, lds, a.uni, inv_tw, post, t);
+        // the first inverse follows a forward transform's round-C reads of
+        // this wave's own half: no entry barrier
+        ntt_inv_reg<LOGN, LEAN>(y, lds, a.uni, inv_tw, post, t, c != c0 || lb != 0);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t part = low32_magic(y[r]);
