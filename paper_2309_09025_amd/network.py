@@ -559,9 +559,11 @@ class UnevenBatch:
         self.capture = capture
         self.pbs_count = 0
 
-    def run(self, px_cts, Ts, Hs):
+    def run(self, px_cts, Ts, Hs, record: bool = False):
         """px_cts: list of device [Ci*H*Wd][n+1]; returns host score
-        ciphertexts per image (input order) and the bootstrapping count."""
+        ciphertexts per image (input order).  record: also return, per
+        timestep, each active image's host copies of H1, S1, V1, H2, S2, V2
+        and its score ({image index: {...}}), one step at a time."""
         ctx, w = self.ctx, self.width
         order = sorted(range(len(px_cts)), key=lambda i: (-Ts[i], i))
         B = len(order)
@@ -597,6 +599,18 @@ class UnevenBatch:
                     F.lwe_linear(ctx, W2, S2[a:b], sc, add=sc)
             return step, 2 * (n1 + n2)
 
+        def snapshot(active):
+            rec = {}
+            for k in range(active):
+                a, b = int(off2[k]), int(off2[k + 1])
+                r1 = slice(k * l1, (k + 1) * l1)
+                rec[order[k]] = {"H1": F.to_host(H1[r1]), "S1": F.to_host(S1[r1]),
+                                 "V1": F.to_host(V1[r1]), "H2": F.to_host(H2[a:b]),
+                                 "S2": F.to_host(S2[a:b]), "V2": F.to_host(V2[a:b]),
+                                 "score": F.to_host(score[k * self.classes:(k + 1) * self.classes])}
+            return rec
+
+        steps = []
         t = 0
         Tmax = Ts_s[0] if B else 0
         while t < Tmax:
@@ -607,10 +621,12 @@ class UnevenBatch:
             for _ in range(span):
                 g.run()
                 self.pbs_count += count
+                if record:
+                    steps.append(snapshot(active))
             t += span
         torch.cuda.synchronize()
         host = F.to_host(score).reshape(B, self.classes, w)
         out = [None] * B
         for k, i in enumerate(order):
             out[i] = host[k]
-        return out
+        return (out, steps) if record else out

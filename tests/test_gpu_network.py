@@ -194,11 +194,18 @@ def test_conv_snn_full_size_sampled(gpu_env, okeys_a):
         assert set(np.unique(v2)) <= {0, 1, 2, -1, -2}
         s1 = F.decrypt(sk, steps[t]["S1"])
         assert set(np.unique(s1)) <= {0, 2}
-    # layer-2 input is the WeightSum of the layer-1 spikes plus V2: linear
-    want_h2 = O.lwe_linear(W1, steps[0]["S1"])
-    assert np.array_equal(steps[0]["H2"], want_h2)
-    want_score = O.lwe_linear(W2, steps[1]["S2"], add=steps[0]["score"])
-    assert np.array_equal(steps[1]["score"], want_score)
+    # layer 2 at every step: its input is the WeightSum of the GPU's own
+    # layer-1 spikes plus V2 (linear, all rows), and the oracle bootstraps
+    # sampled rows of that input (FHE-Fire / FHE-Reset, Sec. 4.2)
+    rows2 = [0, 77, 255]
+    for t in range(cfg.T):
+        V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.hidden, P.n + 1)
+        assert np.array_equal(steps[t]["H2"], O.lwe_linear(W1, steps[t]["S1"], add=V2prev)), t
+        s2, v2 = O.lif_step(okeys_a, cfg.vth, cfg.tau, steps[t]["H2"][rows2])
+        assert np.array_equal(steps[t]["S2"][rows2], s2), t
+        assert np.array_equal(steps[t]["V2"][rows2], v2), t
+        prev = steps[t - 1]["score"] if t else O.zero_ct(cfg.classes, P.n + 1)
+        assert np.array_equal(steps[t]["score"], O.lwe_linear(W2, steps[t]["S2"], add=prev)), t
 
 
 def test_uneven_batch_equals_images_alone(gpu_env):
@@ -286,6 +293,11 @@ def test_paper_csnn_full_size_sampled(gpu_env, okeys_a):
         assert np.array_equal(steps[t]["H2"], O.lwe_linear(W1, pooled, add=V2prev)), t
         V3prev = steps[t - 1]["V3"] if t else O.zero_ct(cfg.classes, P.n + 1)
         assert np.array_equal(steps[t]["H3"], O.lwe_linear(W2, steps[t]["S2"], add=V3prev)), t
+        # the oracle bootstraps sampled rows of both deeper layers' inputs
+        for lay, rows in (("2", [0, 80, 159]), ("3", [0, 5, 9])):
+            s_, v_ = O.lif_step(okeys_a, cfg.vth, cfg.tau, steps[t]["H" + lay][rows])
+            assert np.array_equal(steps[t]["S" + lay][rows], s_), (t, lay)
+            assert np.array_equal(steps[t]["V" + lay][rows], v_), (t, lay)
         for k in ("S1", "S2", "S3"):
             assert set(np.unique(F.decrypt(sk, steps[t][k]))) <= {0, 2}, (t, k)
         for k in ("V1", "V2", "V3"):
@@ -359,6 +371,52 @@ def test_poisson_snn_full_size_sampled(gpu_env, okeys_a):
         assert np.array_equal(steps[t]["H1"], O.lwe_linear(W1, steps[t]["S0"], add=V1prev)), t
         V2prev = steps[t - 1]["V2"] if t else O.zero_ct(cfg.classes, P.n + 1)
         assert np.array_equal(steps[t]["H2"], O.lwe_linear(W2, steps[t]["S1"], add=V2prev)), t
+        # both LIF layers: the oracle bootstraps sampled rows of the GPU's input
+        for lay, rows in (("1", [3, 159]), ("2", [0, 9])):
+            s_, v_ = O.lif_step(okeys_a, cfg.vth, cfg.tau, steps[t]["H" + lay][rows])
+            assert np.array_equal(steps[t]["S" + lay][rows], s_), (t, lay)
+            assert np.array_equal(steps[t]["V" + lay][rows], v_), (t, lay)
         for k in ("S1", "S2"):
             assert set(np.unique(F.decrypt(sk, steps[t][k]))) <= {0, 2}, (t, k)
 
+
+
+def test_uneven_batch_full_size_hidden_800_every_layer(gpu_env, okeys_a):
+    """Two full-size images in one uneven batch, hidden widths 256 and 800
+    and T = 2 and 3: for the 800-wide network the oracle recomputes sampled
+    layer-1 chains from the image, and at every step bootstraps sampled rows
+    of the GPU's own layer-2 input (800 wide), whose WeightSum identity is
+    checked on all rows, as is the score's."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    base = synth.CONV_SNN
+    geom = (base.Ci, base.H, base.Wd, base.stride, base.pad)
+    nets = {}
+    for h in (256, 800):
+        _, Wc, W1, W2 = synth.ConvSNN(hidden=h).data()
+        nets[h] = (W1, W2)
+    pxs = [base.data(image_stream=k)[0] for k in range(2)]
+    cts = [F.to_device(F.encrypt(sk, px, synth.SEED_ENC, 5000 * k)) for k, px in enumerate(pxs)]
+    batch = NW.UnevenBatch(ctx, dk, Wc, nets, geom, NW.LifSpec(base.vth, base.tau))
+    Ts, Hs = [2, 3], [256, 800]
+    scores, steps = batch.run(cts, Ts, Hs, record=True)
+    assert len(steps) == 3 and sorted(steps[2]) == [1]
+    W1, W2 = nets[800]
+    octs = O.encrypt(O.SHAPE_A, okeys_a.s, pxs[1], synth.SEED_ENC, 5000)
+    I1 = O.lwe_conv2d(Wc, octs, base.Ci, base.H, base.Wd, base.stride, base.pad)
+    sample1 = [0, 700, 1567]
+    oH, oS, oV = O.lif_layer_run(okeys_a, I1[sample1], base.vth, base.tau, Ts[1])
+    rows2 = [0, 399, 799]
+    for t in range(Ts[1]):
+        st = steps[t][1]
+        assert st["H2"].shape == (800, P.n + 1)
+        assert np.array_equal(st["H1"][sample1], oH[t]) and np.array_equal(st["S1"][sample1], oS[t])
+        assert np.array_equal(st["V1"][sample1], oV[t]), t
+        V2prev = steps[t - 1][1]["V2"] if t else O.zero_ct(800, P.n + 1)
+        assert np.array_equal(st["H2"], O.lwe_linear(W1, st["S1"], add=V2prev)), t
+        s2, v2 = O.lif_step(okeys_a, base.vth, base.tau, st["H2"][rows2])
+        assert np.array_equal(st["S2"][rows2], s2), t
+        assert np.array_equal(st["V2"][rows2], v2), t
+        prev = steps[t - 1][1]["score"] if t else O.zero_ct(base.classes, P.n + 1)
+        assert np.array_equal(st["score"], O.lwe_linear(W2, st["S2"], add=prev)), t
+    assert np.array_equal(scores[1], steps[-1][1]["score"])
