@@ -563,8 +563,48 @@ def batched(F, synth, shape, B, steps, warmup, cpu_sample, no_cpu, retune, copy_
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    handles = {"P": P, "sk": sk, "ctx": ctx, "dk": dk, "fire": fire, "d_in": d_in}
+    handles = {"P": P, "sk": sk, "evk": evk, "ctx": ctx, "dk": dk, "fire": fire, "d_in": d_in,
+               "d_ext": d_ext, "d_out": d_out}
     return rec, handles
+
+
+def one_limb(F, h, steps, retune):
+    """The same N = 2048 batch with the key in the one-limb form
+    (FS_KEY_ONE_LIMB: whole 32-bit coefficients in the transform, exact for
+    keys generated as the library does): its own context and tuned
+    variant, the step timed like the batched leg, outputs compared with the
+    two-limb form's bit for bit."""
+    import torch
+    from paper_2309_09025_amd import tune
+    P, B = h["P"], h["d_in"].shape[0]
+    ctx = F.Context(0)
+    dk = F.evk_upload(ctx, h["evk"], F.FS_KEY_ONE_LIMB)
+    ctx.reserve(P.N, B)
+    variant, variant_ms = tune.tune_blind_rotation(ctx, dk, B, use_cache=not retune)
+    stream = torch.cuda.current_stream()
+    ext, out = torch.empty_like(h["d_ext"]), torch.empty_like(h["d_out"])
+    F.pbs(ctx, dk, h["fire"], h["d_in"], ext, keyswitch=False, stream=stream)  # warm
+    F.keyswitch(ctx, dk, ext, out, stream=stream)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        e[0].record(stream)
+        F.pbs(ctx, dk, h["fire"], h["d_in"], ext, keyswitch=False, stream=stream)
+        e[1].record(stream)
+        F.keyswitch(ctx, dk, ext, out, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    br = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    ops, _ = alg_ops_per_pbs(P.n, P.N, P.l)
+    ach = ops * B / (br / 1e3) / 1e12
+    return {"form": "FS_KEY_ONE_LIMB", "value": round(B / (ms / 1e3), 2), "unit": "bootstrappings/sec",
+            "ms_per_step": round(ms, 4), "blind_rotate_kernel_ms": round(br, 4),
+            "achieved": round(ach, 3), "frac": round(ach / PEAK_VALU_TOPS, 4),
+            "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
+            "same_bits_as_two_limb_form": bool(torch.equal(ext, h["d_ext"]) and torch.equal(out, h["d_out"])),
+            "resident_key_bytes": dk.nbytes}
 
 
 def ceilings(F):
@@ -697,6 +737,8 @@ def main():
         _log("batched bootstrapping, shape b (N = 2048)")
         shape_b, hb = batched(F, synth, 1, B, max(2, args.steps // 2), 1, args.cpu_sample_b,
                               args.no_cpu_baseline, args.retune, 0)
+        _log("batched bootstrapping, shape b, one-limb key form")
+        shape_b["one_limb_key_form"] = one_limb(F, hb, max(2, args.steps // 2), args.retune)
         del hb
         torch.cuda.synchronize()
         torch.cuda.empty_cache()

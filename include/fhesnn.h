@@ -236,6 +236,32 @@ FS_API int fs_ctx_set_split(fs_ctx* ctx, uint32_t N, size_t max_jobs, size_t* pr
  * device key is immutable afterwards and may be shared by calls on any
  * stream of the context's device. */
 FS_API int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk);
+
+/* Key forms of the NTT-domain BSK (fs_evk_upload_form).  The external
+ * product of a CMux step (Sec. 2.1, RGSW product) sums (k+1) l N products of
+ * digits and key coefficients; the transform returns that integer exactly
+ * while it stays below (p_ntt - 1)/2, p_ntt ~ 2^50.6.
+ *  FS_KEY_EXACT (fs_evk_upload): exact for every key.  At N = 2048,
+ *    Bg = 2^10 the worst case is 2^53, so the 32-bit key coefficients are
+ *    split into two 16-bit limbs: twice the pointwise products and the
+ *    inverse transforms, twice the key bytes (165 MB).
+ *  FS_KEY_ONE_LIMB: the coefficients stay whole (83 MB at N = 2048; the
+ *    same as FS_KEY_EXACT at N = 1024).  For a key generated as fs_keygen
+ *    does, a step's key rows are uniform words independent of that step's
+ *    digits, so every sum is sub-Gaussian with standard deviation at most
+ *    2^45.7 (2^44.9 for the uniform digits of a typical step) and passes
+ *    (p_ntt - 1)/2, 14.7 of those deviations, with probability below
+ *    2^-150 per coefficient (2^-128 per bootstrapping); the outputs are
+ *    then the same bits as FS_KEY_EXACT.  (Rows of the body column are
+ *    uniform when z is invertible mod 2; otherwise the bound grows by the
+ *    index 2^v of the image of multiplication by z.)  A key crafted
+ *    against this bound can only corrupt its own results.  Opt-in. */
+#define FS_KEY_EXACT 0
+#define FS_KEY_ONE_LIMB 1
+FS_API int fs_evk_upload_form(fs_ctx* ctx, const fs_evk* evk, int form, fs_devkey** dk);
+/* FS_KEY_EXACT or FS_KEY_ONE_LIMB (N = 1024 keys report FS_KEY_EXACT), or
+ * a negative error code. */
+FS_API int fs_devkey_form(const fs_devkey* dk);
 FS_API int fs_devkey_params(const fs_devkey* dk, fs_params* out);
 FS_API size_t fs_devkey_bytes(const fs_devkey* dk);
 FS_API void fs_devkey_free(fs_devkey* dk);

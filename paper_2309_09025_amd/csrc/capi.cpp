@@ -31,6 +31,7 @@ struct fs_devkey {
   double* post = nullptr;
   fs::UniTw uni{};  // roots shared by all threads of a transform
   size_t bytes = 0;
+  uint32_t limbs = 1;  // 16-bit key limbs of the NTT-domain BSK (2: N = 2048, exact form)
 };
 
 // Batch-size thresholds of the thread-group forms for one ring degree (see
@@ -293,10 +294,11 @@ int get_tpoly_two(fs_ctx* ctx, uint32_t N, uint32_t p, const int32_t* f0, const 
 }
 
 // thread groups per job for a batch of this size (see launch_blind_rotate),
-// from the context's thresholds for ring degree N, checked in order
-int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs) {
+// from the context's thresholds for ring degree N, checked in order; the
+// one-limb N = 2048 key has no row form and takes two groups there
+int br_groups(const fs_ctx* ctx, uint32_t N, size_t jobs, uint32_t limbs) {
   const GroupLimits g = limits_for(ctx, N);
-  if (jobs <= g.rows) return kBrRows;
+  if (jobs <= g.rows) return N == 2048 && limbs == 1 ? kBrTwo : kBrRows;
   if (N == 1024 && jobs <= g.paired) return kBrTwoPaired;
   return jobs <= g.split ? kBrTwo : kBrOne;
 }
@@ -322,6 +324,7 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   br.inv_tw = dk->inv_tw;
   br.post = dk->post;
   br.uni = dk->uni;
+  br.limbs = dk->limbs;
   if (keyswitch && fixed_ext) {
     br.ext = fixed_ext;
   } else if (keyswitch) {
@@ -331,7 +334,8 @@ int run_pbs(fs_ctx* ctx, const fs_devkey* dk, uint32_t* const tp[2], uint32_t nl
   } else {
     br.ext = out0;
   }
-  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
+  int rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant,
+                                         br_groups(ctx, P.N, jobs, br.limbs), st),
                      "blind rotation");
   if (rc || !keyswitch) return rc;
   KsArgs ks{};
@@ -375,6 +379,8 @@ int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, s
       return fail(FS_EPARAM, "fs_pbs_lif_ranges: keys of different parameter sets");
     if (ranges[k].key->device != ctx->device)
       return fail(FS_EPARAM, "fs_pbs_lif_ranges: a key lives on another device");
+    if (ranges[k].key->limbs != ranges[order[0]].key->limbs)
+      return fail(FS_EPARAM, "fs_pbs_lif_ranges: keys of different key forms");
   }
   if (P.ks_t != 8 || P.ks_base_bit != 2)
     return fail(FS_ENOTSUP, "fs_pbs_lif_ranges: needs the t = 8, base 4 key switch");
@@ -438,10 +444,12 @@ int pbs_lif_ranges(fs_ctx* ctx, const fs_lif* lif, const fs_lif_range* ranges, s
   br.inv_tw = ranges[order[0]].key->inv_tw;
   br.post = ranges[order[0]].key->post;
   br.uni = ranges[order[0]].key->uni;
+  br.limbs = ranges[order[0]].key->limbs;
   br.ext = ctx->ext;
   br.ranges = ctx->ranges;
   br.nranges = (uint32_t)host.size();
-  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, jobs, variant,
+                                     br_groups(ctx, P.N, jobs, br.limbs), st),
                  "blind rotation");
   if (rc) return rc;
   // one batched key switch per key over its adjacent ranges
@@ -713,16 +721,23 @@ int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant) {
 }
 
 int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
+  return fs_evk_upload_form(ctx, evk, FS_KEY_EXACT, dk_out);
+}
+
+int fs_evk_upload_form(fs_ctx* ctx, const fs_evk* evk, int form, fs_devkey** dk_out) {
   if (!ctx || !evk || !dk_out) return fail(FS_EINVAL, "fs_evk_upload: null argument");
+  if (form != FS_KEY_EXACT && form != FS_KEY_ONE_LIMB)
+    return fail(FS_EINVAL, "fs_evk_upload: unknown key form");
   int rc = check_params(&evk->prm);
   if (rc) return rc;
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   const fs_params& P = evk->prm;
-  const uint32_t limbs = P.N == 2048 ? 2 : 1;
+  const uint32_t limbs = P.N == 2048 && form == FS_KEY_EXACT ? 2 : 1;
   auto* dk = new fs_devkey;
   dk->prm = P;
   dk->device = ctx->device;
+  dk->limbs = limbs;
   // The matrix-core key switch (t = 8 digits of base 4) reads the KSK only
   // as byte planes, built on the device from a staging copy that is then
   // freed; other digit shapes keep the uint32 key for the generic kernel.
@@ -756,7 +771,7 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
   e = hipMemcpy(coef, evk->bsk.data(), bsk_words * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(*ksk_dst, evk->ksk.data(), ksk_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return cleanup(hip_fail(e, "fs_evk_upload: copy"));
-  rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, coef, dk->bsk, dk->fwd_tw, nullptr),
+  rc = launch_rc(launch_bsk_to_ntt(P.N, P.n, P.l, limbs, coef, dk->bsk, dk->fwd_tw, nullptr),
                  "BSK conversion");
   if (rc) return cleanup(rc);
   if (planes_form) {
@@ -773,6 +788,11 @@ int fs_evk_upload(fs_ctx* ctx, const fs_evk* evk, fs_devkey** dk_out) {
               (size_t)(5 * P.N / 2) * sizeof(double);
   *dk_out = dk;
   return FS_OK;
+}
+
+int fs_devkey_form(const fs_devkey* dk) {
+  if (!dk) return fail(FS_EINVAL, "null device key");
+  return dk->prm.N == 2048 && dk->limbs == 1 ? FS_KEY_ONE_LIMB : FS_KEY_EXACT;
 }
 
 int fs_devkey_params(const fs_devkey* dk, fs_params* out) {
@@ -967,8 +987,9 @@ int fs_pbs_lif_many_lut(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.inv_tw = dk->inv_tw;
   br.post = dk->post;
   br.uni = dk->uni;
+  br.limbs = dk->limbs;
   br.ext = ctx->ext;
-  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, br_groups(ctx, P.N, B), st),
+  rc = launch_rc(launch_blind_rotate(P.N, br, B, variant, br_groups(ctx, P.N, B, br.limbs), st),
                  "blind rotation");
   if (rc) return rc;
   KsArgs ks{};
@@ -1038,12 +1059,13 @@ int fs_pbs_lif_ks_first(fs_ctx* ctx, const fs_devkey* dk, const fs_lif* lif, con
   br.inv_tw = dk->inv_tw;
   br.post = dk->post;
   br.uni = dk->uni;
+  br.limbs = dk->limbs;
   br.out0 = spike2_out;
   br.out1 = v_out;
   br.plain_b[0] = delta_of(P.p);  // 2S = bootstrap_Fire + 1
   br.plain_b[1] = 0u;
   return launch_rc(
-      launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs), st),
+      launch_blind_rotate(P.N, br, jobs, variant, br_groups(ctx, P.N, jobs, br.limbs), st),
       "blind rotation");
 }
 

@@ -59,6 +59,9 @@ struct BrArgs {
   const JobRange* ranges;
   uint32_t nranges;
   uint64_t jobs;          // jobs in the launch (set by launch_blind_rotate)
+  // 16-bit key limbs of the NTT-domain key: 2 at N = 2048 for exactness
+  // with every key, 1 for the one-limb key form (and always at N = 1024)
+  uint32_t limbs;
 };
 
 struct KsArgs {
@@ -77,8 +80,8 @@ struct KsArgs {
   uint64_t job0;
 };
 
-int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
-                      const double* tw, hipStream_t st);
+int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
+                      const uint32_t* bsk_coef, double* out, const double* tw, hipStream_t st);
 int blind_rotate_variants(uint32_t N);
 // Thread groups per job: 1 (large batches; `variant` picks the tuned
 // instance), 2 (one group per input polynomial) or 0 = one group per digit

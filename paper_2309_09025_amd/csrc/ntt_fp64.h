@@ -20,8 +20,15 @@
 // [-2^31, 2^31), every coefficient of the integer product sum is bounded
 // by 6 * 1024 * 64 * 2^31 = 3 * 2^48 < (P-1)/2, so the centred residue is
 // the integer itself and its low 32 bits are the torus result.  For
-// N = 2048 (4 digit polynomials, |digit| <= 512) the key is split into two
-// 16-bit halves, each product sum then being below 2^37.
+// N = 2048 (4 digit polynomials, |digit| <= 512) the bound for 32-bit key
+// coefficients is 2^53, so the exact key form splits them into two 16-bit
+// halves, each product sum then being below 2^37.  The one-limb key form
+// keeps them whole: a step's key rows are fresh uniform words independent of
+// that step's digits, so each coefficient sum is sub-Gaussian with variance
+// at most 8192 * 512^2 * 2^62 / 3 ((P-1)/2 is 14.7 standard deviations
+// away, 25 for the uniform digits of a typical step) and passes the limit
+// with probability below 2^-150; exact for every key only in the two-limb
+// form.
 //
 // Data layout.  A polynomial of N = 16 * TP coefficients is held by TP
 // threads, 16 values per thread; exponent bits [lo, lo+4) of an index live

@@ -802,15 +802,18 @@ polymul_kernel(const int32_t* __restrict__ d, const uint32_t* __restrict__ b, ui
     if (e_ != hipSuccess) return (int)e_;                     \
   } while (0)
 
-int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_coef, double* out,
-                      const double* tw, hipStream_t st) {
+int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
+                      const uint32_t* bsk_coef, double* out, const double* tw, hipStream_t st) {
   const uint32_t rows = 2 * l;
-  if (N == 1024) {
+  if (N == 1024 && limbs == 1) {
     dim3 g(n * rows * 2, 1);
     bsk_to_ntt_kernel<10, 1><<<g, 64, 0, st>>>(bsk_coef, out, rows, tw);
-  } else if (N == 2048) {
+  } else if (N == 2048 && limbs == 2) {
     dim3 g(n * rows * 2, 2);
     bsk_to_ntt_kernel<11, 2><<<g, 128, 0, st>>>(bsk_coef, out, rows, tw);
+  } else if (N == 2048 && limbs == 1) {
+    dim3 g(n * rows * 2, 1);
+    bsk_to_ntt_kernel<11, 1><<<g, 128, 0, st>>>(bsk_coef, out, rows, tw);
   } else {
     return -1;
   }
@@ -819,10 +822,13 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, const uint32_t* bsk_co
 }
 
 // Kernel variants the tuner chooses from: (PF key-slice prefetch point,
-// minimum waves per SIMD the register allocation must allow).
-// N = 1024: (0, 2), (1, 2), (2, 1), (2, 2); N = 2048: (0, 1), (2, 1), (1, 1),
-// (0, 2).  Split launches (two polynomial groups per job) use (1, 2) at
-// N = 1024 and (0, 1) at N = 2048.
+// minimum waves per SIMD the register allocation must allow), by index:
+// N = 1024: (2, 2), (1, 2), (0, 2), (2, 1); N = 2048, two key limbs: (3, 2),
+// (0, 1), (0, 2), (1, 1); N = 2048, one limb: (2, 2), (1, 2), (0, 2),
+// (3, 2).  Split launches (two polynomial groups per job) use (1, 2) at
+// N = 1024, (0, 1) at N = 2048 with two limbs and (1, 2) with one.  The
+// one-limb N = 2048 key has no row form (two of its four groups would run
+// no inverse transform, so the groups' barrier sequences would differ).
 int blind_rotate_variants(uint32_t N) { return N == 1024 || N == 2048 ? 4 : 0; }
 
 int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant, int groups,
@@ -835,7 +841,7 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
   if (groups == kBrTwoPaired && N == 1024) {
     // two jobs of two groups per workgroup: every SIMD of a CU holds one wave
     blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2, 2><<<dim3((uint32_t)((jobs + 1) / 2)), 256, 0, st>>>(a);
-  } else if (groups == kBrRows) {
+  } else if (groups == kBrRows && !(N == 2048 && a.limbs == 1)) {
     if (N == 1024) blind_rotate_rows_kernel<10, 3, 7, 1><<<g, 6 * 64, 0, st>>>(a);
     else if (N == 2048) blind_rotate_rows_kernel<11, 2, 10, 2><<<g, 4 * 128, 0, st>>>(a);
     else return -1;
@@ -848,6 +854,19 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
         case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 2: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1><<<g, 64, 0, st>>>(a); break;
+        default: return -2;
+      }
+    }
+  } else if (N == 2048 && a.limbs == 1) {
+    if (groups == kBrRows) return -2;
+    if (split) {
+      blind_rotate_kernel<11, 2, 10, 1, 1, 2, 2><<<g, 256, 0, st>>>(a);
+    } else {
+      switch (variant) {
+        case 0: blind_rotate_kernel<11, 2, 10, 1, 2, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 1: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 2: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 1, 3, 2, 1><<<g, 128, 0, st>>>(a); break;
         default: return -2;
       }
     }

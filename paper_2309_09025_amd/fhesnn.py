@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfhesnn.so")
 
 FS_OK, FS_EINVAL, FS_ENOMEM, FS_EDEVICE, FS_EPARAM, FS_EBUDGET, FS_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 FS_PARAMS_VERSION = 1
+FS_KEY_EXACT, FS_KEY_ONE_LIMB = 0, 1
 
 
 class FsError(RuntimeError):
@@ -87,6 +88,8 @@ SIGNATURES = {
     "fs_br_variants": (_int, [_u32]),
     "fs_ctx_set_br_variant": (_int, [_vp, _u32, _int]),
     "fs_evk_upload": (_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "fs_evk_upload_form": (_int, [_vp, _vp, _int, ctypes.POINTER(_vp)]),
+    "fs_devkey_form": (_int, [_vp]),
     "fs_devkey_params": (_int, [_vp, _PP]),
     "fs_devkey_bytes": (_sz, [_vp]),
     "fs_devkey_free": (None, [_vp]),
@@ -118,6 +121,11 @@ def lib():
     """Load libfhesnn.so; raise if it has not been built (no fallback)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the one
+        # the library links: loaded first, it is the one both share (loaded
+        # after the library, torch would run on the library's copy and find
+        # no device)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2309_09025_amd.build`")
@@ -386,13 +394,14 @@ def br_variants(N: int) -> int:
 
 
 class DevKey:
-    def __init__(self, ctx: Context, evk: EvalKey):
+    def __init__(self, ctx: Context, evk: EvalKey, form: int = 0):
         h = ctypes.c_void_p()
-        _check("fs_evk_upload", lib().fs_evk_upload(ctx.h, evk.h, ctypes.byref(h)))
+        _check("fs_evk_upload_form", lib().fs_evk_upload_form(ctx.h, evk.h, form, ctypes.byref(h)))
         self.h = h
         self.ctx = ctx
         self.params = CParams()
         _check("fs_devkey_params", lib().fs_devkey_params(h, ctypes.byref(self.params)))
+        self.form = _check_form(lib().fs_devkey_form(h))
 
     @property
     def nbytes(self) -> int:
@@ -404,8 +413,16 @@ class DevKey:
             self.h = ctypes.c_void_p()
 
 
-def evk_upload(ctx: Context, evk: EvalKey) -> DevKey:
-    return DevKey(ctx, evk)
+def _check_form(rc: int) -> int:
+    if rc < 0:
+        _check("fs_devkey_form", rc)
+    return rc
+
+
+def evk_upload(ctx: Context, evk: EvalKey, form: int = 0) -> DevKey:
+    """form: FS_KEY_EXACT (0, exact for every key) or FS_KEY_ONE_LIMB (1,
+    whole 32-bit key coefficients at N = 2048; see include/fhesnn.h)."""
+    return DevKey(ctx, evk, form)
 
 
 def lwe_linear(ctx: Context, W, x, y, add=None, stream=None):

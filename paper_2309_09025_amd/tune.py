@@ -5,7 +5,7 @@ batch of the caller's shape (bootstrapping runtime does not depend on the
 ciphertext contents, apart from the rare skipped step a~_i = 0, so uniform
 random samples are representative) and keeps the fastest.  Results are
 cached in tune_cache.json next to this file, keyed by
-(GPU architecture, N, l, Bg, batch bucket).
+(GPU architecture, N, l, Bg, key form, batch bucket).
 """
 from __future__ import annotations
 
@@ -27,8 +27,14 @@ def _bucket(jobs: int) -> int:
     return b
 
 
-def _key(arch: str, P, jobs: int) -> str:
-    return f"{arch}|N={P.N}|l={P.l}|bg={P.bg_bit}|jobs={_bucket(jobs)}"
+def _form(dk) -> str:
+    """Cache-key suffix of the device key's form (the one-limb N = 2048 key
+    runs other kernel instances)."""
+    return "|one_limb" if getattr(dk, "form", 0) == F.FS_KEY_ONE_LIMB else ""
+
+
+def _key(arch: str, P, jobs: int, form: str = "") -> str:
+    return f"{arch}|N={P.N}|l={P.l}|bg={P.bg_bit}{form}|jobs={_bucket(jobs)}"
 
 
 def _load():
@@ -66,7 +72,7 @@ def tune_blind_rotation(ctx: F.Context, dk: F.DevKey, jobs: int, reps: int = 2,
     import torch
     P = dk.params
     _check_device(ctx)
-    key = _key(arch_name(ctx.device), P, jobs)
+    key = _key(arch_name(ctx.device), P, jobs, _form(dk))
     cache = _load() if use_cache else {}
     if key in cache:
         best = int(cache[key]["variant"])
@@ -122,18 +128,22 @@ def tune_groups(ctx: F.Context, dk: F.DevKey, intervals: int = 4, reps: int = 2,
     each interval; the forms' times are steps at multiples of the CU count)
     for k = 1..intervals, set the resulting thresholds on ctx and return
     (thresholds, {jobs: {form: ms}}).  The paired form exists at N = 1024
-    only (elsewhere it falls back to two groups and is skipped)."""
+    only (elsewhere it falls back to two groups and is skipped), the row form
+    not for the one-limb N = 2048 key.  The thresholds are the context's for
+    ring degree N, whatever the key form."""
     import torch
     P = dk.params
     _check_device(ctx)
     cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
-    key = f"{arch_name(ctx.device)}|N={P.N}|l={P.l}|bg={P.bg_bit}|groups|cus={cus}"
+    key = f"{arch_name(ctx.device)}|N={P.N}|l={P.l}|bg={P.bg_bit}{_form(dk)}|groups|cus={cus}"
     cache = _load() if use_cache else {}
     if key in cache:
         best = cache[key]["best"]
         times = {int(j): v for j, v in cache[key]["ms"].items()}
     else:
         forms = FORMS if P.N == 1024 else tuple(f for f in FORMS if f != "paired")
+        if _form(dk):  # the one-limb key has no row form (it runs two groups there)
+            forms = tuple(f for f in forms if f != "rows")
         g = np.random.Generator(np.random.PCG64(4321))
         lut = np.where(np.arange(P.p) < P.p // 2, 1, -1).astype(np.int32)
         stream = torch.cuda.current_stream()

@@ -2,8 +2,8 @@
 hipcc cross-compiles).  They guard properties the throughput depends on and
 that a harmless-looking source change can lose without any parity test
 noticing:
-  * the N = 1024 kernels and the default N = 2048 one fit two waves per
-    SIMD without scratch;
+  * the N = 1024 kernels, the default N = 2048 one and the one-limb N = 2048
+    ones fit two waves per SIMD without scratch;
   * no buffer load of the key or the transform tables sits in a waterfall
     loop (a descriptor the compiler cannot prove uniform is re-read lane by
     lane around every load: readfirstlane + 64-bit compare + exec loop)."""
@@ -55,7 +55,9 @@ def _br(usage, args):
 
 @pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1, 1), (10, 3, 7, 1, 1, 2, 1, 1),
                                   (10, 3, 7, 1, 2, 2, 1, 1), (10, 3, 7, 1, 1, 2, 2, 1),
-                                  (10, 3, 7, 1, 1, 2, 2, 2), (11, 2, 10, 2, 3, 2, 1, 1)])
+                                  (10, 3, 7, 1, 1, 2, 2, 2), (11, 2, 10, 2, 3, 2, 1, 1),
+                                  (11, 2, 10, 1, 2, 2, 1, 1), (11, 2, 10, 1, 3, 2, 1, 1),
+                                  (11, 2, 10, 1, 1, 2, 2, 1)])
 def test_two_wave_kernels_have_no_scratch(compiled, args):
     usage, _ = compiled
     _, u = _br(usage, args)
