@@ -60,7 +60,7 @@ extern "C" {
 #define FS_ENOMEM (-2)   /* host or device allocation failed                                  */
 #define FS_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed                        */
 #define FS_EPARAM (-4)   /* key / parameter set mismatch                                      */
-#define FS_EBUDGET (-5)  /* request does not fit the memory budget                            */
+#define FS_EBUDGET (-5)  /* request does not fit the memory budget (fs_ctx_admit)             */
 #define FS_ENOTSUP (-6)  /* parameter set outside what the kernels implement                  */
 
 #define FS_PARAMS_VERSION 1u
@@ -193,6 +193,23 @@ FS_API int fs_ctx_reserve(fs_ctx* ctx, uint32_t N, size_t max_jobs);
  * *retired = buffers replaced by larger ones, held until fs_ctx_destroy
  * (see the conventions above).  Either pointer may be NULL. */
 FS_API int fs_ctx_scratch_bytes(const fs_ctx* ctx, size_t* live, size_t* retired);
+
+/* Admission of a serving loop's requests by device memory (the cloud side
+ * of Sec. 5.3 accepts encrypted requests while memory allows).  A context
+ * carries a budget of device bytes for admitted requests (0 = no budget,
+ * the initial state).  fs_ctx_admit(ctx, bytes) admits a request whose
+ * buffers take `bytes`: FS_EBUDGET, with nothing admitted, when the bytes
+ * already admitted plus `bytes` exceed the budget or when the device
+ * reports fewer than `bytes` free; fs_ctx_release gives them back when the
+ * request leaves (FS_EINVAL if more than admitted).  The context's own
+ * scratch is not counted (fs_ctx_reserve sizes it), so a call on an
+ * admitted request never fails for the budget.  fs_ctx_admission reports
+ * the budget and the admitted bytes (either pointer may be NULL).  Safe
+ * from any host thread. */
+FS_API int fs_ctx_set_budget(fs_ctx* ctx, size_t bytes);
+FS_API int fs_ctx_admit(fs_ctx* ctx, size_t bytes);
+FS_API int fs_ctx_release(fs_ctx* ctx, size_t bytes);
+FS_API int fs_ctx_admission(fs_ctx* ctx, size_t* budget, size_t* admitted);
 
 /* Tuning of the blind-rotation kernel.  Every variant computes the same
  * bits; they differ in when the key slice of a digit row is requested

@@ -66,6 +66,9 @@ struct fs_ctx {
   fs::JobRange* ranges = nullptr;
   size_t ranges_cap = 0;
   std::vector<fs::JobRange> ranges_host;
+  // admission of a serving loop's requests: bytes admitted and their budget
+  // (0 = no budget), guarded by mu
+  size_t budget = 0, admitted = 0;
 };
 
 namespace fs {
@@ -680,6 +683,47 @@ int fs_ctx_scratch_bytes(const fs_ctx* ctx, size_t* live, size_t* retired) {
   if (!ctx) return fail(FS_EINVAL, "null context");
   if (live) *live = ctx->ext_words * sizeof(uint32_t) + ctx->ranges_cap * sizeof(JobRange);
   if (retired) *retired = ctx->retired_bytes;
+  return FS_OK;
+}
+
+int fs_ctx_set_budget(fs_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->budget = bytes;
+  return FS_OK;
+}
+
+int fs_ctx_admit(fs_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->budget && (ctx->admitted > ctx->budget || bytes > ctx->budget - ctx->admitted))
+    return fail(FS_EBUDGET, "fs_ctx_admit: " + std::to_string(bytes) + " bytes do not fit the budget (" +
+                                std::to_string(ctx->admitted) + " of " + std::to_string(ctx->budget) +
+                                " admitted)");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  size_t free_b = 0, total_b = 0;
+  FS_HIP(hipMemGetInfo(&free_b, &total_b));
+  if (bytes > free_b)
+    return fail(FS_EBUDGET, "fs_ctx_admit: " + std::to_string(bytes) + " bytes exceed the " +
+                                std::to_string(free_b) + " free on the device");
+  ctx->admitted += bytes;
+  return FS_OK;
+}
+
+int fs_ctx_release(fs_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (bytes > ctx->admitted) return fail(FS_EINVAL, "fs_ctx_release: more bytes than admitted");
+  ctx->admitted -= bytes;
+  return FS_OK;
+}
+
+int fs_ctx_admission(fs_ctx* ctx, size_t* budget, size_t* admitted) {
+  if (!ctx) return fail(FS_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (budget) *budget = ctx->budget;
+  if (admitted) *admitted = ctx->admitted;
   return FS_OK;
 }
 

@@ -85,6 +85,10 @@ SIGNATURES = {
     "fs_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
     "fs_ctx_destroy": (_int, [_vp]),
     "fs_ctx_reserve": (_int, [_vp, _u32, _sz]),
+    "fs_ctx_set_budget": (_int, [_vp, _sz]),
+    "fs_ctx_admit": (_int, [_vp, _sz]),
+    "fs_ctx_release": (_int, [_vp, _sz]),
+    "fs_ctx_admission": (_int, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "fs_br_variants": (_int, [_u32]),
     "fs_ctx_set_br_variant": (_int, [_vp, _u32, _int]),
     "fs_evk_upload": (_int, [_vp, _vp, ctypes.POINTER(_vp)]),
@@ -352,6 +356,28 @@ class Context:
         threshold) use two thread groups per job and two jobs per workgroup
         (N = 1024 only); returns the previous threshold."""
         return self._set_limit("fs_ctx_set_paired", N, max_jobs)
+
+    def set_budget(self, nbytes: int):
+        """Device bytes admissible for requests (0: no budget)."""
+        _check("fs_ctx_set_budget", lib().fs_ctx_set_budget(self.h, int(nbytes)))
+
+    def admit(self, nbytes: int) -> bool:
+        """Admit a request of nbytes: True, or False when it does not fit the
+        budget or the device's free memory (FS_EBUDGET)."""
+        rc = lib().fs_ctx_admit(self.h, int(nbytes))
+        if rc == FS_EBUDGET:
+            return False
+        _check("fs_ctx_admit", rc)
+        return True
+
+    def release(self, nbytes: int):
+        _check("fs_ctx_release", lib().fs_ctx_release(self.h, int(nbytes)))
+
+    def admission(self):
+        """(budget, admitted) device bytes."""
+        b, a = ctypes.c_size_t(), ctypes.c_size_t()
+        _check("fs_ctx_admission", lib().fs_ctx_admission(self.h, ctypes.byref(b), ctypes.byref(a)))
+        return b.value, a.value
 
     def scratch_bytes(self):
         """(live, retired) device bytes of the context's scratch."""

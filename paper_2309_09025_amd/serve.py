@@ -5,8 +5,10 @@ scores).
 
 * Every registered client's evaluation key stays resident in HBM.
 * A request is admitted when it has arrived and its state buffers fit the
-  device-memory budget; it leaves when its last timestep is done, freeing its
-  memory for the next arrivals.
+  device-memory budget, which the library keeps on the context
+  (fs_ctx_admit: FS_EBUDGET when the admitted bytes would pass the budget or
+  the device's free memory); it leaves when its last timestep is done,
+  releasing its bytes for the next arrivals.  One server per context.
 * One tick advances every in-flight request by one timestep.  Within a tick
   the LIF neurons of a layer of all in-flight requests, whatever their
   client, are bootstrapped by one fs_pbs_lif_ranges launch (each neuron with
@@ -58,7 +60,8 @@ class Server:
     def __init__(self, ctx: F.Context, Wc, nets: dict, geom, lif: LifSpec = LifSpec(),
                  budget_bytes: int = 1 << 30):
         """nets: hidden width -> (W1 [H][l1], W2 [classes][H])."""
-        self.ctx, self.lif, self.budget = ctx, lif, budget_bytes
+        self.ctx, self.lif = ctx, lif
+        self.budget = budget_bytes
         self.Ci, self.H, self.Wd, self.stride, self.pad = geom
         Co, _, K, _ = Wc.shape
         Ho = (self.H + 2 * self.pad - K) // self.stride + 1
@@ -70,9 +73,23 @@ class Server:
         self.classes = next(iter(nets.values()))[1].shape[0]
         self.keys = {}
         self.width = None
-        self.mem_used = 0
         self.pbs_count = 0
         self.ticks = 0
+
+    @property
+    def budget(self) -> int:
+        """Device bytes admissible for in-flight requests (0: no budget)."""
+        return self._budget
+
+    @budget.setter
+    def budget(self, nbytes: int):
+        self._budget = int(nbytes)
+        self.ctx.set_budget(self._budget)
+
+    @property
+    def mem_used(self) -> int:
+        """Bytes of the requests admitted now."""
+        return self.ctx.admission()[1]
 
     # ---------------------------------------------------------------- clients
     def register(self, client: int, evk: F.EvalKey) -> F.DevKey:
@@ -101,7 +118,6 @@ class Server:
                      self.stride, self.pad)
         r.bufs = b
         r.t = 0
-        self.mem_used += self.request_bytes(r.hidden)
 
     # ---------------------------------------------------------------- state
     STATE_KEYS = ("V1", "V2", "score")
@@ -121,7 +137,7 @@ class Server:
         same networks and the client's key registered."""
         if (state["hidden"], state["client"]) != (r.hidden, r.client):
             raise ValueError("checkpoint of a different request")
-        if self.mem_used + self.request_bytes(r.hidden) > self.budget:
+        if not self.ctx.admit(self.request_bytes(r.hidden)):
             raise MemoryError("request does not fit the memory budget")
         self._admit(r)
         for k in self.STATE_KEYS:
@@ -132,7 +148,7 @@ class Server:
         """Drop an in-flight request and free its device memory."""
         if r.bufs:
             r.bufs = {}
-            self.mem_used -= self.request_bytes(r.hidden)
+            self.ctx.release(self.request_bytes(r.hidden))
 
     def step(self, inflight):
         """One tick over the given in-flight requests (each advances one
@@ -150,7 +166,7 @@ class Server:
 
     def admit(self, r: Request):
         """Admit a request now (budget permitting)."""
-        if self.mem_used + self.request_bytes(r.hidden) > self.budget:
+        if not self.ctx.admit(self.request_bytes(r.hidden)):
             raise MemoryError("request does not fit the memory budget")
         self._admit(r)
 
@@ -158,7 +174,7 @@ class Server:
         r.score = F.to_host(r.bufs["score"])
         r.done = now
         r.bufs = {}
-        self.mem_used -= self.request_bytes(r.hidden)
+        self.ctx.release(self.request_bytes(r.hidden))
 
     def _tick(self, inflight):
         c, L = self.ctx, self.lif
@@ -189,13 +205,14 @@ class Server:
         inflight = []
         t0 = time.perf_counter()
         max_req = max(self.request_bytes(h) for h in self.nets)
-        if max_req > self.budget:
+        if self.budget and max_req > self.budget:
             raise ValueError("budget smaller than one request")
         while pending or inflight:
             now = time.perf_counter() - t0
-            # admission: arrived requests, in order, while memory allows
+            # admission: arrived requests, in order, while the library admits
+            # them (budget and free device memory)
             while pending and pending[0].arrival <= now and \
-                    self.mem_used + self.request_bytes(pending[0].hidden) <= self.budget:
+                    self.ctx.admit(self.request_bytes(pending[0].hidden)):
                 r = pending.popleft()
                 self._admit(r)
                 inflight.append(r)

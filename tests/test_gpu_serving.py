@@ -154,10 +154,37 @@ def test_checkpoint_and_resume_on_another_server_is_byte_identical(gpu_env, clie
         done = second.step([r2])
     assert np.array_equal(r2.score, whole.score)
 
-    tiny = _server(ctx2, base, widths, budget=1)
+    tiny = _server(F.Context(0), base, widths, budget=1)  # one server per context
     tiny.keys, tiny.width = second.keys, second.width
     with pytest.raises(MemoryError):
         tiny.resume(SV.Request(3, cid, ct, T, H), state)
     second.admit(r3 := SV.Request(4, cid, ct, T, H))
     second.cancel(r3)
     assert second.mem_used == 0
+
+
+def test_admission_by_device_memory_returns_fs_ebudget(gpu_env):
+    """fs_ctx_admit / fs_ctx_release through the C ABI: requests are admitted
+    while their bytes fit the budget, FS_EBUDGET (nothing admitted) past it
+    or past the device's free memory, released bytes admit the next one."""
+    ctx = F.Context(0)
+    L = F.lib()
+    assert ctx.admission() == (0, 0)
+    ctx.set_budget(1000)
+    assert L.fs_ctx_admit(ctx.h, 600) == F.FS_OK
+    assert L.fs_ctx_admit(ctx.h, 600) == F.FS_EBUDGET
+    assert "budget" in L.fs_last_error().decode()
+    assert ctx.admission() == (1000, 600)
+    assert ctx.admit(400) and not ctx.admit(1)
+    ctx.release(600)
+    assert ctx.admit(500) and ctx.admission() == (1000, 900)
+    with pytest.raises(F.FsError) as ei:
+        ctx.release(901)
+    assert ei.value.code == F.FS_EINVAL
+    ctx.release(900)
+    # no budget: the device's free memory still bounds a request
+    ctx.set_budget(0)
+    total = torch.cuda.get_device_properties(0).total_memory
+    assert L.fs_ctx_admit(ctx.h, 2 * total) == F.FS_EBUDGET
+    assert ctx.admit(1 << 20) and ctx.admission() == (0, 1 << 20)
+    ctx.release(1 << 20)
