@@ -52,22 +52,25 @@ def alg_ops_per_pbs(n, N, l, limbs=1):
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
-def _traffic(shape, batch):
-    """HBM bytes per blind-rotation launch from the committed counter runs, or
+# blind-rotation instances by workload: (N, l, Bg bits, key limbs)
+BR_INSTANCE = {"a": "blind_rotate_kernel<10,3,7,1,", "b": "blind_rotate_kernel<11,2,10,2,",
+               "b_one_limb": "blind_rotate_kernel<11,2,10,1,"}
+
+
+def _traffic(which, batch):
+    """HBM bytes per blind-rotation launch of the batch from the committed
+    counter runs (the largest grid of the workload's kernel instance), or
     None when the kernel sources changed since they were taken."""
     import glob
+    prefix = BR_INSTANCE[which]
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as fh:
             rec = json.load(fh)
         if rec.get("sources") != KERNEL_SOURCES or _sources_sha() != rec["source_sha"]:
             continue
-        N = 1024 if shape == 0 else 2048
-        if rec.get("N", 1024) != N:
-            continue
         br = [v for name, v in rec.items()
-              if name.startswith("blind_rotate_kernel") and isinstance(v, dict)
-              and v.get("batch") == batch]
-        if br:  # the batch's own launch is the largest blind-rotation grid
+              if name.startswith(prefix) and isinstance(v, dict) and v.get("batch") == batch]
+        if br:  # the batch's own launch is the largest grid of the instance
             return max(br, key=lambda v: v["grid"])["hbm_bytes_per_launch"]
     return None
 
@@ -85,11 +88,12 @@ def _sources_sha():
     return h.hexdigest()[:16]
 
 
-def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path, N=1024):
+def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
     dispatch) of `bench.py --no-networks --copy-mib M` into HBM bytes per
-    launch of each kernel, calibrated by the plain copy of M MiB that run
-    also made (the largest copyBuffer dispatch)."""
+    launch of each kernel instance (both shapes and key forms when the run
+    had them), calibrated by the plain copy of M MiB that run also made
+    (the largest copyBuffer dispatch)."""
     import csv
     import glob
     from collections import defaultdict
@@ -108,7 +112,7 @@ def ingest_counters(fetch_dir, write_dir, batch, copy_mib, out_path, N=1024):
     cf = max(v for _, v in fetch[copy_key])
     cw = max(v for _, v in write[copy_key])
     copy_kib = copy_mib * 1024.0
-    rec = {"source_sha": _sources_sha(), "sources": KERNEL_SOURCES, "N": N,
+    rec = {"source_sha": _sources_sha(), "sources": KERNEL_SOURCES,
            "calibration": {"copy_MiB": copy_mib, "fetch_kib": cf, "write_kib": cw,
                            "fetch_factor": round(copy_kib / cf, 4),
                            "write_factor": round(copy_kib / cw, 4)}}
@@ -510,7 +514,7 @@ def batched(F, synth, shape, B, steps, warmup, cpu_sample, no_cpu, retune, copy_
         "bound": "alu", "kernel": "blind_rotate_kernel",
         "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
         "unit": "TOP/s (binary64 VALU lane-instructions)",
-        "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": _traffic(shape, B),
+        "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": _traffic("ab"[shape], B),
         "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
         "kernel_ms": round(br_avg, 4),
         "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
@@ -602,7 +606,7 @@ def one_limb(F, h, steps, retune):
     return {"form": "FS_KEY_ONE_LIMB", "value": round(B / (ms / 1e3), 2), "unit": "bootstrappings/sec",
             "ms_per_step": round(ms, 4), "blind_rotate_kernel_ms": round(br, 4),
             "achieved": round(ach, 3), "frac": round(ach / PEAK_VALU_TOPS, 4),
-            "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
+            "traffic": _traffic("b_one_limb", B), "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
             "same_bits_as_two_limb_form": bool(torch.equal(ext, h["d_ext"]) and torch.equal(out, h["d_out"])),
             "resident_key_bytes": dk.nbytes}
 
@@ -686,10 +690,8 @@ def main():
                     help="write profiles/traffic_*.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
     if args.ingest_counters:
-        P = {"a": (630, 1024), "b": (630, 2048)}[args.shape]
-        out = os.path.join(ROOT, "profiles",
-                           f"traffic_batched_pbs_n{P[0]}_N{P[1]}_B{args.batch}.json")
-        rec = ingest_counters(*args.ingest_counters, args.batch, args.copy_mib or 256, out, N=P[1])
+        out = os.path.join(ROOT, "profiles", f"traffic_batched_pbs_n630_B{args.batch}.json")
+        rec = ingest_counters(*args.ingest_counters, args.batch, args.copy_mib or 256, out)
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
