@@ -515,12 +515,15 @@ def batched(F, synth, shape, B, steps, warmup, cpu_sample, no_cpu, retune, copy_
         "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
         "unit": "TOP/s (binary64 VALU lane-instructions)",
         "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": _traffic("ab"[shape], B),
+        "traffic_gbs": None,
         "alg_ops_per_pbs": ops, "alg_modmuls_per_pbs": modmuls,
         "kernel_ms": round(br_avg, 4),
         "variant": variant, "variant_ms": {str(k): round(v, 3) for k, v in variant_ms.items()},
         # batch-size thresholds of the thread-group forms (tuned, in jobs)
         "group_limits": dict(zip(("rows", "paired", "split"), group_limits)),
     }
+    if roofline["traffic"]:  # HBM bytes past L2 per launch over the launch time
+        roofline["traffic_gbs"] = round(roofline["traffic"] / (br_avg / 1e3) / 1e9, 1)
     if limbs > 1:
         # the same time against the work the kernel must do with the key in
         # two 16-bit limbs (2x the products and the inverse transforms)
@@ -730,10 +733,22 @@ def main():
     roofline, cpu = main_rec["roofline"], main_rec["cpu_baseline"]
     if not args.no_ceiling:
         _log("measured ceilings (binary64 VALU issue, HBM copy)")
-        roofline["measured_ceiling"] = ceilings(F)
-        c2 = roofline["measured_ceiling"]["valu_butterfly_tops"].get("2")
+        ceil = ceilings(F)
+        roofline["measured_ceiling"] = ceil
+        c2 = ceil["valu_butterfly_tops"].get("2")
         if c2:
+            # the kernel runs 2 waves per SIMD: its ceiling is the probe's rate at 2
             roofline["frac_of_measured_2wave_butterfly_ceiling"] = round(roofline["achieved"] / c2, 4)
+            # R_mm: modular products per second of the probe's butterflies (8
+            # instructions each), against the kernel's algorithmic products
+            r_mm = c2 * 1e12 / BFLY_OPS
+            mm = roofline["alg_modmuls_per_pbs"] * B / (roofline["kernel_ms"] / 1e3)
+            roofline["measured_modmul_rate_R_mm"] = round(r_mm / 1e12, 4)
+            roofline["alg_modmul_rate"] = round(mm / 1e12, 4)
+            roofline["frac_of_R_mm"] = round(mm / r_mm, 4)
+        if roofline["traffic"]:
+            roofline["traffic_gbs_vs_hbm_copy"] = round(
+                roofline["traffic_gbs"] / ceil["hbm_copy_gbs"], 4)
     shape_b = None
     if shape == 0 and not args.no_shape_b:
         _log("batched bootstrapping, shape b (N = 2048)")

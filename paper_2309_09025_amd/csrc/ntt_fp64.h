@@ -367,22 +367,31 @@ __device__ __forceinline__ void fwd_roundA_uni(double x[16], const UniTw& u) {
 // jobs; `entry` then places a workgroup barrier before the first LDS write
 // (needed unless the caller's last access to the buffer was a transform's
 // round-B/C half of its own wave, see exchange).
-template <int LOGN, int DONE = 0, bool LEAN = false>
+//
+// HELD: the per-thread roots of rounds B and C come from `held` (R::FB then
+// R::FC values, loaded once per thread with load_fwd_roots: they depend on
+// the thread only) instead of being requested for every transform.
+template <int LOGN, int DONE = 0, bool LEAN = false, bool HELD = false>
 __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const UniTw& u,
-                                            const Tab& tw, int t, bool entry = true) {
+                                            const Tab& tw, int t, bool entry = true,
+                                            const double* held = nullptr) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B: stages BHI..4, round C: 3..0
   static_assert(DONE >= 0 && DONE <= 2, "at most two stages by table");
-  double wb[R::FB];
-  load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb, tw, t);
+  double wb_own[HELD ? 1 : R::FB];
+  const double* wb = wb_own;
+  if constexpr (HELD) wb = held;
+  else load_fwd_lane<LOGN, S::LOB, BHI, 4>(wb_own, tw, t);
   fwd_roundA_uni<LOGN, LOGN - 1 - DONE>(x, u);
   if constexpr (LEAN && S::TP > 64) {
     if (entry) __syncthreads();
   }
   exchange<LOGN, S::LOA, S::LOB, LEAN>(x, lds, t);
-  double wc[R::FC];
-  load_fwd_lane<LOGN, 0, 3, 0>(wc, tw, t);
+  double wc_own[HELD ? 1 : R::FC];
+  const double* wc = wc_own;
+  if constexpr (HELD) wc = held + R::FB;
+  else load_fwd_lane<LOGN, 0, 3, 0>(wc_own, tw, t);
   fwd_stages_reg<LOGN, S::LOB, BHI, BHI, BHI>(x, wb);  // fifth stage
   reduce16<S::N>(x);
   fwd_stages_reg<LOGN, S::LOB, BHI, BHI - 1, 4>(x, wb);
@@ -391,6 +400,15 @@ __device__ __forceinline__ void ntt_fwd_reg(double x[16], double* lds, const Uni
   fwd_stages_reg<LOGN, 0, 3, 3, LOGN - 9>(x, wc);
   reduce16<S::N>(x);
   fwd_stages_reg<LOGN, 0, 3, LOGN - 10, 0>(x, wc);
+}
+
+// Every per-thread root of a forward transform's rounds B and C (see
+// ntt_fwd_reg's HELD form): RegTw<LOGN>::FWD values.
+template <int LOGN>
+__device__ __forceinline__ void load_fwd_roots(double* w, const Tab& tw, int t) {
+  using S = NttShape<LOGN>;
+  load_fwd_lane<LOGN, S::LOB, LOGN - 5, 4>(w, tw, t);
+  load_fwd_lane<LOGN, 0, 3, 0>(w + RegTw<LOGN>::FB, tw, t);
 }
 
 template <int LOGN, int LO, int SLO, int SHI>

@@ -121,9 +121,16 @@ __device__ __forceinline__ void digit_row_two_stages(const uint32_t d[16], uint3
 // that a batch of up to 2 x CUs jobs occupies every SIMD once: two separate
 // two-wave workgroups on one CU may share two of its SIMDs.  Both jobs then
 // pass the same workgroup barriers, so neither skips a step (a step with
-// a~_i = 0 adds zero, so the bits are the same); the second half of the
-// last workgroup of an odd batch repeats the last job without writing.
-template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W, int JPW = 1>
+// a~_i = 0 adds zero, so the bits are the same); the last workgroup of a
+// batch that JPW does not divide repeats the last job without writing.
+//
+// JPW > 1 with W = 1 (lockstep form): the jobs a CU holds at once share one
+// workgroup and a barrier at the end of every CMux step, so they read the
+// same key rows within a short window and all but the first find them in
+// the CU's L1 (one step's slice is 96 KiB at N = 1024, a digit row 16 KiB),
+// where separate workgroups drift apart and each streams the key from L2.
+template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W, int JPW = 1,
+          bool HELD = false>
 __global__ void __launch_bounds__(JPW * W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
@@ -132,7 +139,7 @@ blind_rotate_kernel(BrArgs a) {
   constexpr uint32_t NU = LOGN + 1;  // log2(2N)
   constexpr int G = 2 * LIMBS;       // key values per slot and digit row
   static_assert(W == 1 || W == 2, "one or two polynomial groups per job");
-  static_assert(JPW == 1 || (JPW == 2 && W == 2), "paired jobs use two groups each");
+  static_assert(JPW == 1 || W == 1 || (JPW == 2 && W == 2), "paired jobs use two groups each");
   static_assert(16 * TP <= S::LDS_DOUBLES, "a partial sum fits an exchange buffer");
   __shared__ double lds_all[JPW * W][S::LDS_DOUBLES];
   __shared__ uint32_t acc_all[JPW][2][N];
@@ -199,6 +206,11 @@ blind_rotate_kernel(BrArgs a) {
     fill_stage_tables<HALF>(stage1, a.uni, threadIdx.x, JPW * W * TP);
     if constexpr (JPW * W * TP > 64) __syncthreads();  // every wave reads the whole table
   }
+
+  // HELD: the forward transforms' per-thread roots, loaded once for the job
+  // (they depend on the thread only) instead of once per transform
+  double held[HELD ? RegTw<LOGN>::FWD : 1];
+  if constexpr (HELD) load_fwd_roots<LOGN>(held, fwd_tw, t);
 
   // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
   {
@@ -286,7 +298,8 @@ blind_rotate_kernel(BrArgs a) {
         }
         // entry barrier of the exchange buffer: not before a step's first
         // transform (the previous step ended with one)
-        ntt_fwd_reg<LOGN, TAB1 ? 2 : 0, LEAN>(xd, lds, a.uni, fwd_tw, t, c != c0 || lv != 0);
+        ntt_fwd_reg<LOGN, TAB1 ? 2 : 0, LEAN, HELD>(xd, lds, a.uni, fwd_tw, t,
+                                                    c != c0 || lv != 0, held);
         if constexpr (PF == 0 || PF == 3) {
 #pragma unroll
           for (int h = 0; h < 16 / KCH; ++h) {
@@ -340,7 +353,11 @@ blind_rotate_kernel(BrArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][t + TP * r] += upd[r];
     }
-    poly_sync<TP>();
+    // one-group jobs sharing a workgroup stay in step (lockstep form): the
+    // key rows the first of them loads are still in the CU's L1 when the
+    // others read them
+    if constexpr (W == 1 && JPW > 1) __syncthreads();
+    else poly_sync<TP>();
   }
   if constexpr (W == 2) __syncthreads();  // the extraction reads both accumulators
 
@@ -822,14 +839,18 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
 }
 
 // Kernel variants the tuner chooses from: (PF key-slice prefetch point,
-// minimum waves per SIMD the register allocation must allow), by index:
-// N = 1024: (2, 2), (1, 2), (0, 2), (2, 1); N = 2048, two key limbs: (3, 2),
-// (0, 1), (0, 2), (1, 1); N = 2048, one limb: (2, 2), (1, 2), (0, 2),
-// (3, 2).  Split launches (two polynomial groups per job) use (1, 2) at
+// minimum waves per SIMD the register allocation must allow[, jobs per
+// workgroup of the lockstep form]), by index:
+// N = 1024: (2, 2), (1, 2), (0, 2), (2, 1), (2, 1, 8), (0, 2, 8), (2, 1, 4),
+// and (0, 2), (3, 2), (1, 2) with the forward roots held in registers;
+// N = 2048, two key limbs: (3, 2), (0, 1), (0, 2), (1, 1), (3, 2, 4),
+// (3, 2, 2), (0, 2, 2), (1, 1, 2), (0, 1, 2); N = 2048, one limb: (2, 2),
+// (1, 2), (0, 2), (0, 2, 2) with held forward roots, (1, 2, 4), (1, 2, 2),
+// and (3, 2), (0, 2), (1, 2) with held forward roots.  Split launches (two polynomial groups per job) use (1, 2) at
 // N = 1024, (0, 1) at N = 2048 with two limbs and (1, 2) with one.  The
 // one-limb N = 2048 key has no row form (two of its four groups would run
 // no inverse transform, so the groups' barrier sequences would differ).
-int blind_rotate_variants(uint32_t N) { return N == 1024 || N == 2048 ? 4 : 0; }
+int blind_rotate_variants(uint32_t N) { return N == 1024 ? 10 : N == 2048 ? 9 : 0; }
 
 int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant, int groups,
                         hipStream_t st) {
@@ -849,11 +870,18 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
     if (split) {
       blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);
     } else {
+      const dim3 g8((uint32_t)((jobs + 7) / 8)), g4((uint32_t)((jobs + 3) / 4));
       switch (variant) {
         case 0: blind_rotate_kernel<10, 3, 7, 1, 2, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 1: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 2: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1><<<g, 64, 0, st>>>(a); break;
         case 3: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1><<<g, 64, 0, st>>>(a); break;
+        case 4: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1, 8><<<g8, 512, 0, st>>>(a); break;
+        case 5: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1, 8><<<g8, 512, 0, st>>>(a); break;
+        case 6: blind_rotate_kernel<10, 3, 7, 1, 2, 1, 1, 4><<<g4, 256, 0, st>>>(a); break;
+        case 7: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
+        case 8: blind_rotate_kernel<10, 3, 7, 1, 3, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
+        case 9: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
         default: return -2;
       }
     }
@@ -862,11 +890,17 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
     if (split) {
       blind_rotate_kernel<11, 2, 10, 1, 1, 2, 2><<<g, 256, 0, st>>>(a);
     } else {
+      const dim3 g4((uint32_t)((jobs + 3) / 4)), g2((uint32_t)((jobs + 1) / 2));
       switch (variant) {
         case 0: blind_rotate_kernel<11, 2, 10, 1, 2, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 1: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 2: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<11, 2, 10, 1, 3, 2, 1><<<g, 128, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 2, true><<<g2, 256, 0, st>>>(a); break;
+        case 4: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 4><<<g4, 512, 0, st>>>(a); break;
+        case 5: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 2><<<g2, 256, 0, st>>>(a); break;
+        case 6: blind_rotate_kernel<11, 2, 10, 1, 3, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
+        case 7: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
+        case 8: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
         default: return -2;
       }
     }
@@ -874,11 +908,17 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
     if (split) {
       blind_rotate_kernel<11, 2, 10, 2, 0, 1, 2><<<g, 256, 0, st>>>(a);
     } else {
+      const dim3 g4((uint32_t)((jobs + 3) / 4)), g2((uint32_t)((jobs + 1) / 2));
       switch (variant) {
         case 0: blind_rotate_kernel<11, 2, 10, 2, 3, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 1: blind_rotate_kernel<11, 2, 10, 2, 0, 1, 1><<<g, 128, 0, st>>>(a); break;
         case 2: blind_rotate_kernel<11, 2, 10, 2, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 3: blind_rotate_kernel<11, 2, 10, 2, 1, 1, 1><<<g, 128, 0, st>>>(a); break;
+        case 4: blind_rotate_kernel<11, 2, 10, 2, 3, 2, 1, 4><<<g4, 512, 0, st>>>(a); break;
+        case 5: blind_rotate_kernel<11, 2, 10, 2, 3, 2, 1, 2><<<g2, 256, 0, st>>>(a); break;
+        case 6: blind_rotate_kernel<11, 2, 10, 2, 0, 2, 1, 2><<<g2, 256, 0, st>>>(a); break;
+        case 7: blind_rotate_kernel<11, 2, 10, 2, 1, 1, 1, 2><<<g2, 256, 0, st>>>(a); break;
+        case 8: blind_rotate_kernel<11, 2, 10, 2, 0, 1, 1, 2><<<g2, 256, 0, st>>>(a); break;
         default: return -2;
       }
     }

@@ -65,7 +65,7 @@ def test_one_limb_pbs_bit_exact(one_limb, okeys_b, keyswitch):
                                             keyswitch=keyswitch))
 
 
-@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("variant", range(9))
 def test_one_limb_every_variant_bit_exact(one_limb, okeys_b, variant):
     P, sk, evk, ctx, dk = one_limb
     m, ct = _inputs(P, sk, okeys_b, 5, 1500 + 5 * variant)

@@ -90,11 +90,14 @@ def test_full_batch_in_the_benchmarked_configuration_sampled(gpu_env, okeys_a, o
     assert np.array_equal(got[idx], want), variant
 
 
-@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("variant", range(10))
 def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
+    """Every N = 1024 variant (prefetch points, register budgets, the
+    lockstep form with 4 or 8 jobs per workgroup, held forward roots) on a
+    batch of 8 (a lockstep workgroup of 8 fully used, or partly empty with 4)."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
-    assert F.br_variants(P.N) == 4
+    assert F.br_variants(P.N) == 10
     m, ct = _pbs_inputs(P, sk, okeys_a, 8, first=200 + 8 * variant)
     f = O.lut_reset(P.p, 4, 2)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
@@ -108,12 +111,15 @@ def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     assert np.array_equal(got, O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct, keyswitch=False))
 
 
-@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("variant", range(9))
 def test_every_blind_rotation_variant_shape_b_bit_exact(gpu_env, okeys_b, variant):
+    """Every N = 2048 variant of the exact two-limb key (lockstep pairs
+    included) on 5 ciphertexts: an odd count, so the last lockstep pair
+    repeats a job without writing."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(1)
-    assert F.br_variants(P.N) == 4
-    m, ct = _pbs_inputs(P, sk, okeys_b, 2, first=600 + 2 * variant)
+    assert F.br_variants(P.N) == 9
+    m, ct = _pbs_inputs(P, sk, okeys_b, 5, first=600 + 5 * variant)
     f = O.lut_fire(P.p, 4)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")
     ctx.set_br_variant(P.N, variant)
@@ -391,3 +397,4 @@ def test_two_group_forms_beyond_one_workgroup_per_cu(gpu_env, okeys_a, mode):
     idx = [0, 300, count - 2, count - 1]
     want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=True)
     assert np.array_equal(_host(out)[idx], want)
+

@@ -46,9 +46,10 @@ def compiled(tmp_path_factory):
     return usage, text
 
 
-def _br(usage, args):
-    """Resource record of blind_rotate_kernel<args...>."""
-    mangled = "_ZN2fs19blind_rotate_kernelI" + "".join(f"Li{a}E" for a in args) + "EEvNS_6BrArgsE"
+def _br(usage, args, held=False):
+    """Resource record of blind_rotate_kernel<args..., held>."""
+    mangled = ("_ZN2fs19blind_rotate_kernelI" + "".join(f"Li{a}E" for a in args)
+               + f"Lb{int(held)}E" + "EEvNS_6BrArgsE")
     assert mangled in usage, sorted(k for k in usage if "blind_rotate" in k)
     return mangled, usage[mangled]
 
@@ -56,11 +57,24 @@ def _br(usage, args):
 @pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1, 1), (10, 3, 7, 1, 1, 2, 1, 1),
                                   (10, 3, 7, 1, 2, 2, 1, 1), (10, 3, 7, 1, 1, 2, 2, 1),
                                   (10, 3, 7, 1, 1, 2, 2, 2), (11, 2, 10, 2, 3, 2, 1, 1),
-                                  (11, 2, 10, 1, 2, 2, 1, 1), (11, 2, 10, 1, 3, 2, 1, 1),
-                                  (11, 2, 10, 1, 1, 2, 2, 1)])
+                                  (11, 2, 10, 1, 2, 2, 1, 1), (11, 2, 10, 1, 1, 2, 2, 1),
+                                  (10, 3, 7, 1, 2, 1, 1, 8), (10, 3, 7, 1, 0, 2, 1, 8)])
 def test_two_wave_kernels_have_no_scratch(compiled, args):
     usage, _ = compiled
     _, u = _br(usage, args)
+    assert u.get("ScratchSize", 0) == 0, u
+    assert u.get("Occupancy", 0) >= 2, u
+
+
+@pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1, 1), (10, 3, 7, 1, 3, 2, 1, 1),
+                                  (10, 3, 7, 1, 1, 2, 1, 1), (11, 2, 10, 1, 3, 2, 1, 1),
+                                  (11, 2, 10, 1, 0, 2, 1, 1), (11, 2, 10, 1, 1, 2, 1, 1),
+                                  (11, 2, 10, 1, 0, 2, 1, 2)])
+def test_held_root_kernels_fit_two_waves_without_scratch(compiled, args):
+    """The variants holding the forward transforms' roots in registers for
+    the whole job (the tuned ones at N = 1024 and for the one-limb key)."""
+    usage, _ = compiled
+    _, u = _br(usage, args, held=True)
     assert u.get("ScratchSize", 0) == 0, u
     assert u.get("Occupancy", 0) >= 2, u
 
@@ -85,3 +99,17 @@ def test_row_kernel_uses_lds_float_atomics(compiled, args):
     body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
     assert "ds_add_f64" in body or "ds_add_rtn_f64" in body
     assert "ds_cmpst" not in body and "ds_cmpswap" not in body
+
+
+def test_tuned_two_limb_lockstep_kernel_spills_only_outside_its_loop(compiled):
+    """The tuned N = 2048 two-limb kernel (two jobs per workgroup in
+    lockstep) sits at 256 registers with one value spilled: allowed only as
+    one store and one reload in the whole kernel (prologue and extraction
+    epilogue), never a spill inside the CMux loop."""
+    usage, text = compiled
+    name, u = _br(usage, (11, 2, 10, 2, 3, 2, 1, 2))
+    assert u.get("Occupancy", 0) >= 2, u
+    assert u.get("ScratchSize", 0) <= 8, u
+    body = text[text.index(name + ":"):]
+    body = body[:body.index("s_endpgm")]
+    assert len(re.findall(r"scratch_(load|store)", body)) <= 2
