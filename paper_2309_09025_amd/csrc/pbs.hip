@@ -70,16 +70,29 @@ __device__ __forceinline__ void digit_row_two_stages(const uint32_t d[16], uint3
                                                      const double* tab, double xd[16]) {
   constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr int TW = 2 * HALF;
+  // All twelve lookups of the row are requested before any is used (the
+  // scheduling barrier keeps the compiler from interleaving them with the
+  // sums, which it otherwise does into one set of registers, waiting for
+  // each group of three in turn).
+  double m1[4], a1[4], b1[4], a3[4], b3[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const double d0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
     const uint32_t f1 = __builtin_amdgcn_ubfe(d[r + 4], sh, BG);
     const uint32_t f2 = __builtin_amdgcn_ubfe(d[r + 8], sh, BG);
     const uint32_t f3 = __builtin_amdgcn_ubfe(d[r + 12], sh, BG);
-    const double m1 = tab[f2];
-    const double lo = d0 + m1, hi = d0 - m1;
-    const double ma = tab[TW + f1] + tab[2 * TW + f3];
-    const double mb = tab[2 * TW + f1] + tab[TW + f3];
+    m1[r] = tab[f2];
+    a1[r] = tab[TW + f1];
+    b1[r] = tab[2 * TW + f1];
+    a3[r] = tab[TW + f3];
+    b3[r] = tab[2 * TW + f3];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double d0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[r], sh, BG) - (int32_t)HALF);
+    const double lo = d0 + m1[r], hi = d0 - m1[r];
+    const double ma = a1[r] + b3[r];
+    const double mb = b1[r] + a3[r];
     xd[r] = lo + ma;
     xd[r + 4] = lo - ma;
     xd[r + 8] = hi + mb;
