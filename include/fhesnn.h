@@ -225,11 +225,13 @@ FS_API int fs_ctx_set_br_variant(fs_ctx* ctx, uint32_t N, int variant);
  * (1024 or 2048; else FS_ENOTSUP).  A launch of B jobs (ciphertexts x
  * program functions) takes the first form whose threshold it does not
  * exceed, in this order; every form computes the same bits:
- *  - rows (fs_ctx_set_rows): 2l groups of N/16 threads per job, one per
- *    digit row of the external product (Sec. 2.1, RGSW product), so a CMux
- *    step's critical path is one forward and one inverse transform: the
- *    lowest latency for one bootstrapping or a few.  Default: the device's
- *    compute units.
+ *  - rows (fs_ctx_set_rows): one thread group per digit row of the external
+ *    product (Sec. 2.1, RGSW product), so a CMux step's critical path is
+ *    one forward and one inverse transform: the lowest latency for one
+ *    bootstrapping or a few.  At N = 1024 each row is split further into
+ *    its two transform halves (2l x 2 waves per job, and the inverse
+ *    transforms on four waves); at N = 2048, 2l groups of N/16 threads.
+ *    Default: the device's compute units.
  *  - paired (fs_ctx_set_paired, N = 1024 only): the two-group form below
  *    with two jobs per workgroup, so that every SIMD of a CU holds one
  *    wave.  Default: 2 x the compute units at N = 1024, 0 at N = 2048.

@@ -84,8 +84,10 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
                       const uint32_t* bsk_coef, double* out, const double* tw, hipStream_t st);
 int blind_rotate_variants(uint32_t N);
 // Thread groups per job: 1 (large batches; `variant` picks the tuned
-// instance), 2 (one group per input polynomial) or 0 = one group per digit
-// row (2l groups, N = 1024 only; smallest batches, latency).
+// instance), 2 (one group per input polynomial), 3 (two such jobs per
+// workgroup, N = 1024) or 0 = one group per digit row (smallest batches,
+// latency; at N = 1024 one wave per digit-row half, at N = 2048 with the
+// two-limb key only).
 enum BrGroups { kBrOne = 1, kBrTwo = 2, kBrRows = 0, kBrTwoPaired = 3 };
 int launch_blind_rotate(uint32_t N, const BrArgs& a, size_t jobs, int variant, int groups,
                         hipStream_t st);

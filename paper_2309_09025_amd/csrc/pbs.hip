@@ -412,6 +412,8 @@ blind_rotate_kernel(BrArgs a) {
 // its low 32 bits (shifted by 16 per limb) into ACC with 32-bit atomics
 // (wrapping mod 2^32, again order-free).  A step's critical path is one
 // forward and one inverse transform.  Same bits as blind_rotate_kernel.
+// Launched at N = 2048; at N = 1024 blind_rotate_halfrow_kernel (below)
+// spreads the same work over all four SIMDs.
 template <int LOGN, int L, int BG, int LIMBS>
 __global__ void __launch_bounds__(2 * L * NttShape<LOGN>::TP)
 blind_rotate_rows_kernel(BrArgs a) {
@@ -545,6 +547,374 @@ blind_rotate_rows_kernel(BrArgs a) {
       }
     }
     __syncthreads();  // ACC updated and the sums cleared before the next step
+  }
+
+#pragma unroll
+  for (uint32_t k = 0; k < 2; ++k) {
+    if (k > even) break;
+    const uint32_t fn = even ? k : lut;
+    uint32_t* out;
+    uint32_t plain = 0u;
+    if (a.out0) {
+      out = (fn == 0 ? a.out0 : a.out1) + g * (size_t)(N + 1);
+      plain = a.plain_b[fn];
+    } else {
+      out = a.ext + (even ? 2 * job + k : job) * (size_t)(N + 1);
+    }
+    out = uniform_ptr(out);
+    for (int j = tid; j < N; j += NT) out[j] = j <= (int)k ? acc[0][k - j] : 0u - acc[0][N + k - j];
+    if (tid == 0) out[N] = acc[1][k] + plain;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation for latency at N = 1024 in half rows.  After the first
+// forward stage (pairs j, j + N/2) the two halves of a digit row's
+// transform are independent: the remaining stages act within each half with
+// the roots of the full transform.  Likewise the inverse's stages 0 .. 8 act
+// within the halves of the bit-reversed order, and only its last stage
+// pairs i with i + N/2.  So a job runs as 2l x 2 = 12 waves, one per (digit
+// row, half), 8 values per thread, three per SIMD in the forward phase (the
+// one-wave-per-row kernel puts two rows on two of the four SIMDs), and the
+// 2 x 2 (output, half) inverse transforms run on four waves, one per SIMD.
+// The stages, roots, reduction points and products are those of the other
+// kernels, so the bits are the same.
+//
+// A half of 512 values is held by 64 threads, 8 values each; exponent bits
+// [LO, LO + 3) of its index live in the register number:
+//     j'(t, r) = (t & (2^LO - 1)) | (r << LO) | ((t >> LO) << (LO + 3)),
+// with forward rounds at LO = 6 (stages 7, 6), 3 (5, 4, 3) and 0 (2, 1, 0)
+// and the inverse walking them back (stages 0-2, 3-5, 6-8).
+template <int LO>
+__device__ __forceinline__ int hmap(int t, int r) {
+  return (t & ((1 << LO) - 1)) | (r << LO) | ((t >> LO) << (LO + 3));
+}
+
+// Exchange of one wave's half between register mappings through its own LDS
+// buffer (in-order within the wave: compiler fences only).  The padded slot
+// of j'(t, r) splits into a thread part and a register part as in exchange.
+template <int FROM, int TO>
+__device__ __forceinline__ void hexchange(double x[8], double* lds, int t) {
+  double* wp = lds + lds_slot(hmap<FROM>(t, 0));
+  const double* rp = lds + lds_slot(hmap<TO>(t, 0));
+#pragma unroll
+  for (int r = 0; r < 8; ++r) wp[lds_slot(r << FROM)] = x[r];
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) x[r] = rp[lds_slot(r << TO)];
+  wave_sync();
+}
+
+__device__ __forceinline__ void reduce8(double x[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) x[r] = redc(x[r]);
+}
+
+// One stage in a round: pairs registers r and r | 2^b, root w[r >> (b+1)]
+// (forward, decimation in frequency).
+template <int B, int NW>
+__device__ __forceinline__ void hfwd_stage(double x[8], const double* w) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << B)) continue;
+    const int r2 = r | (1 << B);
+    const double m = mulmod(x[r2], w[(r >> (B + 1)) % NW]);
+    x[r2] = x[r] - m;
+    x[r] = x[r] + m;
+  }
+}
+
+// Inverse stage in a round: pairs r and r | 2^b, root w[r & (2^b - 1)].
+template <int B>
+__device__ __forceinline__ void hinv_stage(double x[8], const double* w) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << B)) continue;
+    const int r2 = r | (1 << B);
+    const double m = mulmod(x[r2], w[r & ((1 << B) - 1)]);
+    x[r2] = x[r] - m;
+    x[r] = x[r] + m;
+  }
+}
+
+// Per-thread roots of half h, loaded once per job.  Forward (index k of
+// psi^{brv(k)}, stage s: k = N/2^{s+1} + j/2^{s+1}, j = 512 h + j'):
+//   round B: stage 5: 16 + 8h + t/8; 4: 32 + 16h + 2(t/8) + e; 3: 64 + 32h + 4(t/8) + e
+//   round C: stage 2: 128 + 64h + t; 1: 256 + 128h + 2t + e; 0: 512 + 256h + 4t + e
+// Inverse (index e of omega^-e, stage s: e = (i mod 2^s) N/2^{s+1}; the
+// halves share stages 0-8):
+//   round B': stage 3: 64 (t&7); 4: 32 ((t&7) | 8e); 5: 16 ((t&7) | 8e)
+//   round A': stage 6: 8t; 7: 4 (t | 64e); 8: 2 (t | 64e)
+//   stage 9: i' = t | 64 r; twist psi^-j N^-1 at j = 512 h + t + 64 r.
+struct HalfRoots {
+  double f5, f4[2], f3[4], f2, f1[2], f0[4];
+};
+// inverse roots of a thread, by stage: offsets into HalfInvRoots::w
+enum HalfInv { kI3 = 0, kI4 = 1, kI5 = 3, kI6 = 7, kI7 = 8, kI8 = 10, kI9 = 14, kTw = 22,
+               kHalfInvRoots = 30 };
+struct HalfInvRoots {
+  double w[kHalfInvRoots];
+};
+__device__ __forceinline__ void load_half_roots(HalfRoots& w, const Tab& tw, int t, uint32_t h) {
+  const uint32_t tb = (uint32_t)t >> 3;
+  w.f5 = tw.at(tb * 8u, (16u + 8u * h) * 8u);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) w.f4[e] = tw.at(2u * tb * 8u, (32u + 16u * h + e) * 8u);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w.f3[e] = tw.at(4u * tb * 8u, (64u + 32u * h + e) * 8u);
+  w.f2 = tw.at((uint32_t)t * 8u, (128u + 64u * h) * 8u);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) w.f1[e] = tw.at(2u * t * 8u, (256u + 128u * h + e) * 8u);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w.f0[e] = tw.at(4u * t * 8u, (512u + 256u * h + e) * 8u);
+}
+__device__ __forceinline__ void load_half_inv_roots(HalfInvRoots& w, const Tab& itw,
+                                                    const Tab& post, int t, uint32_t h) {
+  const uint32_t t7 = (uint32_t)t & 7u, tt = (uint32_t)t;
+  w.w[kI3] = itw.at(64u * t7 * 8u, 0);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) w.w[kI4 + e] = itw.at(32u * t7 * 8u, 32u * 8u * e * 8u);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w.w[kI5 + e] = itw.at(16u * t7 * 8u, 16u * 8u * e * 8u);
+  w.w[kI6] = itw.at(8u * tt * 8u, 0);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) w.w[kI7 + e] = itw.at(4u * tt * 8u, 4u * 64u * e * 8u);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w.w[kI8 + e] = itw.at(2u * tt * 8u, 2u * 64u * e * 8u);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) w.w[kI9 + r] = itw.at(tt * 8u, 64u * r * 8u);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) w.w[kTw + r] = post.at(tt * 8u, (512u * h + 64u * r) * 8u);
+}
+
+// Digits of half h after the first two forward stages by table: the quads
+// of digit_row_two_stages (registers q, q + 4, q + 8, q + 12 of d hold
+// positions j, j + 256, j + 512, j + 768, j = t + 64 q); half 0 keeps
+// positions j and j + 256 (d0 + i d2 +- (d1 w2 + d3 w3)), half 1 keeps
+// j + 512 and j + 768 (d0 - i d2 +- (d1 w3 + d3 w2)).  Output in the
+// round-A mapping of the half: x[q] at j' = t + 64 q, x[q + 4] at + 256.
+template <int BG>
+__device__ __forceinline__ void digit_half_two_stages(const uint32_t d[16], uint32_t sh,
+                                                      const double* tab, uint32_t h,
+                                                      double x[8]) {
+  constexpr uint32_t HALF = 1u << (BG - 1);
+  constexpr uint32_t TW = 2 * HALF;
+  const uint32_t oa = h ? 2 * TW : TW, ob = h ? TW : 2 * TW;
+  double m1[4], ma[4], mb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    m1[q] = tab[__builtin_amdgcn_ubfe(d[q + 8], sh, BG)];
+    ma[q] = tab[oa + __builtin_amdgcn_ubfe(d[q + 4], sh, BG)];
+    mb[q] = tab[ob + __builtin_amdgcn_ubfe(d[q + 12], sh, BG)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double d0 = (double)((int32_t)__builtin_amdgcn_ubfe(d[q], sh, BG) - (int32_t)HALF);
+    const double base = h ? d0 - m1[q] : d0 + m1[q];
+    const double m = ma[q] + mb[q];
+    x[q] = base + m;
+    x[q + 4] = base - m;
+  }
+}
+
+// Forward stages 7 .. 0 of half h (stages 9 and 8 done by table): the
+// reduction points of ntt_fwd_reg (after stage 5 and after stage 1).  Out:
+// round-C mapping, x[r] at bit-reversed position 512 h + 8 t + r, |x| < 1.14 P.
+__device__ __forceinline__ void ntt_fwd_half(double x[8], double* lds, const UniTw& u,
+                                             const HalfRoots& w, uint32_t h, int t) {
+  // round A (uniform roots): stage 7, k = 4 + 2h + r/4; stage 6, k = 8 + 4h + r/2
+  double a7[2], a6[4];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) a7[e] = h ? u.fwd[6 + e] : u.fwd[4 + e];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a6[e] = h ? u.fwd[12 + e] : u.fwd[8 + e];
+  hfwd_stage<1, 2>(x, a7);
+  hfwd_stage<0, 4>(x, a6);
+  hexchange<6, 3>(x, lds, t);
+  hfwd_stage<2, 1>(x, &w.f5);
+  reduce8(x);
+  hfwd_stage<1, 2>(x, w.f4);
+  hfwd_stage<0, 4>(x, w.f3);
+  hexchange<3, 0>(x, lds, t);
+  hfwd_stage<2, 1>(x, &w.f2);
+  hfwd_stage<1, 2>(x, w.f1);
+  reduce8(x);
+  hfwd_stage<0, 4>(x, w.f0);
+}
+
+// Inverse stages 0 .. 8 of one half (input |x| < 5 P in the round-C
+// mapping): reductions before stages 0, 3 and 7 as in ntt_inv_reg.  Out:
+// round-A mapping, x[r] at i' = t + 64 r.
+__device__ __forceinline__ void ntt_inv_half(double x[8], double* lds, const UniTw& u,
+                                             const HalfInvRoots& w, int t) {
+  reduce8(x);
+#pragma unroll
+  for (int s = 0; s <= 2; ++s) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r & (1 << s)) continue;
+      const int r2 = r | (1 << s);
+      const int m8 = (r & ((1 << s) - 1)) << (3 - s);  // e = m8 N / 16
+      const double m = m8 == 0 ? x[r2] : mulmod(x[r2], u.inv[m8]);
+      x[r2] = x[r] - m;
+      x[r] = x[r] + m;
+    }
+  }
+  reduce8(x);
+  hexchange<0, 3>(x, lds, t);
+  hinv_stage<0>(x, w.w + kI3);
+  hinv_stage<1>(x, w.w + kI4);
+  hinv_stage<2>(x, w.w + kI5);
+  hexchange<3, 6>(x, lds, t);
+  hinv_stage<0>(x, w.w + kI6);
+  reduce8(x);
+  hinv_stage<1>(x, w.w + kI7);
+  hinv_stage<2>(x, w.w + kI8);
+}
+
+template <int L, int BG>
+__global__ void __launch_bounds__(4 * L * 64)
+blind_rotate_halfrow_kernel(BrArgs a) {
+  constexpr int LOGN = 10, N = 1024, TP = 64, ROWS = 2 * L, NW = 2 * ROWS, G = 2;
+  constexpr uint32_t HALF = 1u << (BG - 1);
+  constexpr uint32_t NU = LOGN + 1;
+  static_assert(NW >= 4, "four waves run the inverse transforms");
+  __shared__ double lds_all[NW][512 + 32];
+  __shared__ double sums[2][2][8][TP];  // [output][half][r][t]
+  __shared__ uint32_t acc[2][N];
+  __shared__ double stage1[6 * HALF];
+  // the inverse transforms' per-thread roots of each half, [half][root][t]:
+  // loaded once, read for every transform (the key stream evicts them from
+  // the L1 cache between steps, and held in registers they would cost the
+  // forward phase its spill-free allocation)
+  __shared__ double iroots[2][kHalfInvRoots][TP];
+
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TP);
+  const int t = (int)threadIdx.x - wv * TP;
+  const int rowi = wv >> 1;  // digit row c l + lv
+  const uint32_t h = (uint32_t)wv & 1u;
+  const int c = rowi / L, lv = rowi % L;
+  double* lds = lds_all[wv];
+  const size_t job = blockIdx.x;
+  const uint32_t n = a.n;
+  const uint64_t g = a.nlut == 2 ? job >> 1 : job;
+  const uint32_t lut = a.nlut == 2 ? (uint32_t)(job & 1u) : 0u;
+  const uint32_t* ct;
+  const double* bsk;
+  if (a.ranges) {
+    const JobRange& rg = a.ranges[find_range(a.ranges, a.nranges, g)];
+    ct = rg.in + (g - rg.first) * (size_t)(n + 1);
+    bsk = rg.bsk;
+  } else {
+    ct = a.in + g * (size_t)(n + 1);
+    bsk = a.bsk;
+  }
+  ct = uniform_ptr(ct);
+  bsk = uniform_ptr(bsk);
+  const Tab key(bsk), fwd_tw(a.fwd_tw), inv_tw(a.inv_tw), post(a.post);
+  const uint32_t* v = lut == 0 ? a.tpoly0 : a.tpoly1;
+
+  uint32_t off = 1u << (31 - L * BG);
+#pragma unroll
+  for (int j = 1; j <= L; ++j) off += HALF << (32 - j * BG);
+  const uint32_t even = __builtin_amdgcn_readfirstlane(a.even);
+  const uint32_t msh = 32 - NU + even, mhalf = 1u << (msh - 1);
+  auto mod_switch = [=](uint32_t x) { return ((x + mhalf) >> msh) << even; };
+
+  const int tid = threadIdx.x;
+  constexpr int NT = NW * TP;
+  fill_stage_tables<HALF>(stage1, a.uni, tid, NT);
+  for (int j = tid; j < 2 * 2 * 8 * TP; j += NT) (&sums[0][0][0][0])[j] = 0.0;
+  {
+    const uint32_t bbar = mod_switch(ct[n]);
+    const uint32_t e = (2 * N - bbar) & (2 * N - 1);
+    for (int j = tid; j < N; j += NT) {
+      const int src = j - (int)e;
+      uint32_t val;
+      if (src >= 0) val = v[src];
+      else if (src + N >= 0) val = 0u - v[src + N];
+      else val = v[src + 2 * N];
+      acc[0][j] = 0u;
+      acc[1][j] = val;
+    }
+  }
+  HalfRoots fw;
+  load_half_roots(fw, fwd_tw, t, h);
+  // the four inverse waves: (output wv >> 1, half wv & 1)
+  const bool inv = wv < 4;
+  const int co = wv >> 1;
+  if (wv < 2) {
+    HalfInvRoots iw;
+    load_half_inv_roots(iw, inv_tw, post, t, h);
+#pragma unroll
+    for (int k = 0; k < kHalfInvRoots; ++k) iroots[h][k][t] = iw.w[k];
+  }
+  __syncthreads();
+
+  const uint32_t sh = 32 - (lv + 1) * BG;
+  // key of position 512 h + 8 t + r: slot (r16, t16) = (8 (t & 1) + r, 32 h + t / 2)
+  // of the row, G doubles each
+  const uint32_t kv_lane = (((uint32_t)t & 1u) * 512u + ((uint32_t)t >> 1)) * (G * 8);
+  const uint32_t kv_half = 32u * h * (G * 8);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t abar = mod_switch(ct[i]);
+    if (abar == 0) continue;
+    const uint32_t row = i * (uint32_t)(ROWS * 16 * TP * G * 8) +
+                         (uint32_t)(rowi * 16 * TP * G * 8) + kv_half;
+    double kv[8][G];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      key.at2(kv_lane, row + (uint32_t)(r * TP * G * 8), kv[r][0], kv[r][1]);
+    double x[8];
+    {
+      uint32_t d[16];
+      const uint32_t* ac = acc[c];
+      const int kb = t - (int)abar;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = kb + TP * r;
+        const uint32_t val = ac[k & (N - 1)];
+        const uint32_t neg = 0u - (((uint32_t)k >> LOGN) & 1u);
+        d[r] = ((val ^ neg) - neg) - ac[t + TP * r] + off;
+      }
+      digit_half_two_stages<BG>(d, sh, stage1, h, x);
+    }
+    ntt_fwd_half(x, lds, a.uni, fw, h, t);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int q = 0; q < G; ++q) atomicAdd(&sums[q][h][r][t], mulmod(x[r], kv[r][q]));
+    __syncthreads();  // every product is in; every rotation has read ACC
+    double y[8];
+    HalfInvRoots iw;
+    if (inv) {
+#pragma unroll
+      for (int k = 0; k < kHalfInvRoots; ++k) iw.w[k] = iroots[h][k][t];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        y[r] = sums[co][h][r][t];
+        sums[co][h][r][t] = 0.0;  // cleared for the next step
+      }
+      ntt_inv_half(y, lds, a.uni, iw, t);
+      // the last inverse stage pairs i' and 512 + i' across the two halves
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[r * TP + t] = y[r];
+    }
+    __syncthreads();  // both halves of each output are in LDS
+    if (inv) {
+      const double* other = lds_all[wv ^ 1];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double o = other[r * TP + t];
+        double z;
+        if (h == 0) z = y[r] + mulmod(o, iw.w[kI9 + r]);
+        else z = o - mulmod(y[r], iw.w[kI9 + r]);
+        const uint32_t part = low32_magic(redc(mulmod(z, iw.w[kTw + r])));
+        acc[co][512 * h + t + TP * r] += part;
+      }
+    }
+    __syncthreads();  // ACC updated and the half buffers read before the next step
   }
 
 #pragma unroll
@@ -876,7 +1246,7 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
     // two jobs of two groups per workgroup: every SIMD of a CU holds one wave
     blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2, 2><<<dim3((uint32_t)((jobs + 1) / 2)), 256, 0, st>>>(a);
   } else if (groups == kBrRows && !(N == 2048 && a.limbs == 1)) {
-    if (N == 1024) blind_rotate_rows_kernel<10, 3, 7, 1><<<g, 6 * 64, 0, st>>>(a);
+    if (N == 1024) blind_rotate_halfrow_kernel<3, 7><<<g, 12 * 64, 0, st>>>(a);
     else if (N == 2048) blind_rotate_rows_kernel<11, 2, 10, 2><<<g, 4 * 128, 0, st>>>(a);
     else return -1;
   } else if (N == 1024) {

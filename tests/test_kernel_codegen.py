@@ -88,17 +88,26 @@ def test_no_waterfall_loops_in_blind_rotation(compiled):
         assert "v_cmp_eq_u64" not in body, name
 
 
-@pytest.mark.parametrize("args", [(10, 3, 7, 1), (11, 2, 10, 2)])
-def test_row_kernel_uses_lds_float_atomics(compiled, args):
-    """The row kernel sums the rows' products with hardware LDS binary64
-    atomic adds (a compare-and-swap loop would serialise them)."""
+@pytest.mark.parametrize("name", ["_ZN2fs24blind_rotate_rows_kernelILi11ELi2ELi10ELi2EEEvNS_6BrArgsE",
+                                  "_ZN2fs27blind_rotate_halfrow_kernelILi3ELi7EEEvNS_6BrArgsE"])
+def test_row_kernels_use_lds_float_atomics(compiled, name):
+    """The latency kernels (one group per digit row at N = 2048, one wave per
+    digit row half at N = 1024) sum the rows' products with hardware LDS
+    binary64 atomic adds (a compare-and-swap loop would serialise them), and
+    use no scratch."""
     usage, text = compiled
-    name = "_ZN2fs24blind_rotate_rows_kernelI" + "".join(f"Li{a}E" for a in args) + "EEvNS_6BrArgsE"
-    assert name in usage, sorted(k for k in usage if "rows" in k)
+    assert name in usage, sorted(k for k in usage if "row" in k)
     assert usage[name].get("ScratchSize", 0) == 0
     body = text.split(f"\n{name}:", 1)[1].split("s_endpgm", 1)[0]
     assert "ds_add_f64" in body or "ds_add_rtn_f64" in body
     assert "ds_cmpst" not in body and "ds_cmpswap" not in body
+
+
+def test_half_row_kernel_fits_its_twelve_waves(compiled):
+    """12 waves per job, three per SIMD: at most 168 registers."""
+    usage, _ = compiled
+    u = usage["_ZN2fs27blind_rotate_halfrow_kernelILi3ELi7EEEvNS_6BrArgsE"]
+    assert u.get("VGPRs", 0) + u.get("AGPRs", 0) <= 168, u
 
 
 def test_tuned_two_limb_lockstep_kernel_spills_only_outside_its_loop(compiled):
