@@ -398,3 +398,22 @@ def test_two_group_forms_beyond_one_workgroup_per_cu(gpu_env, okeys_a, mode):
     want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=True)
     assert np.array_equal(_host(out)[idx], want)
 
+
+
+@pytest.mark.parametrize("count,first", [(1, 9400), (1, 9401), (300, 9500)])
+def test_half_row_latency_kernel_bit_exact(gpu_env, okeys_a, count, first):
+    """The N = 1024 latency form (one wave per digit-row half, 12 per job)
+    alone for one bootstrapping, and forced onto more jobs than the device
+    has CUs (several workgroups per CU in turn): outputs before the key
+    switch equal the oracle's (every row of one job, sampled rows of 300)."""
+    ctx, get = gpu_env
+    P, sk, evk, dk = get(0)
+    m, ct = _pbs_inputs(P, sk, okeys_a, count, first=first)
+    f = O.lut_reset(P.p, 4, 2)
+    out = torch.zeros((count, P.N + 1), dtype=torch.int32, device="cuda")
+    with ctx.groups("rows"):
+        F.pbs(ctx, dk, f, _dev(ct), out, keyswitch=False)
+        got = _host(out)
+    idx = list(range(count)) if count < 4 else [0, 150, count - 1]
+    want = O.pbs(okeys_a, O.test_poly(P.N, P.p, f), ct[idx], keyswitch=False)
+    assert np.array_equal(got[idx], want)
