@@ -469,16 +469,21 @@ __device__ __forceinline__ void inv_roundC_uni(double x[16], const UniTw& u, int
 // psi^-j N^-1 and a reduction, giving the exact centred residue in round-A
 // mapping (thread t, register r: coefficient t + TP r).  The per-thread roots
 // of each round are requested one round ahead.
-// LEAN and `entry` as for ntt_fwd_reg.
-template <int LOGN, bool LEAN = false>
+// LEAN and `entry` as for ntt_fwd_reg.  HELD: the per-thread roots of rounds
+// B' (HELD >= 1) and A' (HELD = 2) come from `held` (R::IB then R::IA values,
+// loaded once with load_inv_roots) instead of being requested for every
+// transform.
+template <int LOGN, bool LEAN = false, int HELD = 0>
 __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const UniTw& u,
                                             const Tab& itw, const Tab& post, int t,
-                                            bool entry = true) {
+                                            bool entry = true, const double* held = nullptr) {
   using S = NttShape<LOGN>;
   using R = RegTw<LOGN>;
   constexpr int BHI = LOGN - 5;  // round B': stages 4..BHI, round A': BHI+1..LOGN-1
-  double wb[R::IB];
-  load_inv_lane<LOGN, S::LOB, 4, BHI>(wb, itw, t);
+  double wb_own[HELD >= 1 ? 1 : R::IB];
+  const double* wb = wb_own;
+  if constexpr (HELD >= 1) wb = held;
+  else load_inv_lane<LOGN, S::LOB, 4, BHI>(wb_own, itw, t);
   reduce16<S::N>(x);
   inv_roundC_uni<LOGN>(x, u, 0, 2);
   reduce16<S::N>(x);
@@ -487,8 +492,10 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
     if (entry) __syncthreads();
   }
   exchange<LOGN, 0, S::LOB, LEAN>(x, lds, t);
-  double wa[R::IA];
-  load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wa, itw, t);
+  double wa_own[HELD == 2 ? 1 : R::IA];
+  const double* wa = wa_own;
+  if constexpr (HELD == 2) wa = held + R::IB;
+  else load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(wa_own, itw, t);
   inv_stages_reg<LOGN, S::LOB, 4, 4, BHI>(x, wb);
   exchange<LOGN, S::LOB, S::LOA, LEAN>(x, lds, t);
   double wp[16];
@@ -504,6 +511,16 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = redc(mulmod(x[r], wp[r]));
+}
+
+// The per-thread roots of an inverse transform's rounds B' and A' (see
+// ntt_inv_reg's HELD form): RegTw<LOGN>::IB + IA values (round B' only when
+// ROUNDS = 1).
+template <int LOGN, int ROUNDS = 2>
+__device__ __forceinline__ void load_inv_roots(double* w, const Tab& itw, int t) {
+  using S = NttShape<LOGN>;
+  load_inv_lane<LOGN, S::LOB, 4, LOGN - 5>(w, itw, t);
+  if constexpr (ROUNDS == 2) load_inv_lane<LOGN, S::LOA, LOGN - 4, LOGN - 1>(w + RegTw<LOGN>::IB, itw, t);
 }
 
 // Low 32 bits of an integer-valued double e with |e| < 2^51: e + 1.5 * 2^52

@@ -143,7 +143,7 @@ __device__ __forceinline__ void digit_row_two_stages(const uint32_t d[16], uint3
 // the CU's L1 (one step's slice is 96 KiB at N = 1024, a digit row 16 KiB),
 // where separate workgroups drift apart and each streams the key from L2.
 template <int LOGN, int L, int BG, int LIMBS, int PF, int WPE, int W, int JPW = 1,
-          bool HELD = false>
+          bool HELD = false, int HELDI = 0>
 __global__ void __launch_bounds__(JPW * W * NttShape<LOGN>::TP, WPE)
 blind_rotate_kernel(BrArgs a) {
   using S = NttShape<LOGN>;
@@ -224,6 +224,10 @@ blind_rotate_kernel(BrArgs a) {
   // (they depend on the thread only) instead of once per transform
   double held[HELD ? RegTw<LOGN>::FWD : 1];
   if constexpr (HELD) load_fwd_roots<LOGN>(held, fwd_tw, t);
+  // HELDI: likewise the inverse transforms' roots of round B' (1) or of
+  // rounds B' and A' (2)
+  double heldi[HELDI ? RegTw<LOGN>::IB + (HELDI == 2 ? RegTw<LOGN>::IA : 0) : 1];
+  if constexpr (HELDI) load_inv_roots<LOGN, HELDI>(heldi, inv_tw, t);
 
   // Initialization: ACC = (0, X^{-b~} v), b~ = round(b 2N / 2^32)
   {
@@ -356,7 +360,8 @@ blind_rotate_kernel(BrArgs a) {
         double* y = c == 0 ? p0[lb] : p1[lb];
         // the first inverse follows a forward transform's round-C reads of
         // this wave's own half: no entry barrier
-        ntt_inv_reg<LOGN, LEAN>(y, lds, a.uni, inv_tw, post, t, c != c0 || lb != 0);
+        ntt_inv_reg<LOGN, LEAN, HELDI>(y, lds, a.uni, inv_tw, post, t, c != c0 || lb != 0,
+                                       heldi);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t part = low32_magic(y[r]);
@@ -1225,7 +1230,8 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
 // minimum waves per SIMD the register allocation must allow[, jobs per
 // workgroup of the lockstep form]), by index:
 // N = 1024: (2, 2), (1, 2), (0, 2), (2, 1), (2, 1, 8), (0, 2, 8), (2, 1, 4),
-// and (0, 2), (3, 2), (1, 2) with the forward roots held in registers;
+// and (0, 2), (3, 2), (1, 2) with the forward roots held in registers, and
+// (0, 2) with the forward and the inverse transforms' roots held;
 // N = 2048, two key limbs: (3, 2), (0, 1), (0, 2), (1, 1), (3, 2, 4),
 // (3, 2, 2), (0, 2, 2), (1, 1, 2), (0, 1, 2); N = 2048, one limb: (2, 2),
 // (1, 2), (0, 2), (0, 2, 2) with held forward roots, (1, 2, 4), (1, 2, 2),
@@ -1233,7 +1239,7 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
 // N = 1024, (0, 1) at N = 2048 with two limbs and (1, 2) with one.  The
 // one-limb N = 2048 key has no row form (two of its four groups would run
 // no inverse transform, so the groups' barrier sequences would differ).
-int blind_rotate_variants(uint32_t N) { return N == 1024 ? 10 : N == 2048 ? 9 : 0; }
+int blind_rotate_variants(uint32_t N) { return N == 1024 ? 11 : N == 2048 ? 9 : 0; }
 
 int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant, int groups,
                         hipStream_t st) {
@@ -1265,6 +1271,7 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
         case 7: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
         case 8: blind_rotate_kernel<10, 3, 7, 1, 3, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
         case 9: blind_rotate_kernel<10, 3, 7, 1, 1, 2, 1, 1, true><<<g, 64, 0, st>>>(a); break;
+        case 10: blind_rotate_kernel<10, 3, 7, 1, 0, 2, 1, 1, true, 2><<<g, 64, 0, st>>>(a); break;
         default: return -2;
       }
     }

@@ -90,14 +90,15 @@ def test_full_batch_in_the_benchmarked_configuration_sampled(gpu_env, okeys_a, o
     assert np.array_equal(got[idx], want), variant
 
 
-@pytest.mark.parametrize("variant", range(10))
+@pytest.mark.parametrize("variant", range(11))
 def test_every_blind_rotation_variant_bit_exact(gpu_env, okeys_a, variant):
     """Every N = 1024 variant (prefetch points, register budgets, the
-    lockstep form with 4 or 8 jobs per workgroup, held forward roots) on a
+    lockstep form with 4 or 8 jobs per workgroup, held forward roots, held
+    forward and inverse roots) on a
     batch of 8 (a lockstep workgroup of 8 fully used, or partly empty with 4)."""
     ctx, get = gpu_env
     P, sk, evk, dk = get(0)
-    assert F.br_variants(P.N) == 10
+    assert F.br_variants(P.N) == 11
     m, ct = _pbs_inputs(P, sk, okeys_a, 8, first=200 + 8 * variant)
     f = O.lut_reset(P.p, 4, 2)
     out = torch.zeros((len(m), P.N + 1), dtype=torch.int32, device="cuda")

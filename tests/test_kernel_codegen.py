@@ -46,10 +46,10 @@ def compiled(tmp_path_factory):
     return usage, text
 
 
-def _br(usage, args, held=False):
-    """Resource record of blind_rotate_kernel<args..., held>."""
+def _br(usage, args, held=False, heldi=0):
+    """Resource record of blind_rotate_kernel<args..., held, heldi>."""
     mangled = ("_ZN2fs19blind_rotate_kernelI" + "".join(f"Li{a}E" for a in args)
-               + f"Lb{int(held)}E" + "EEvNS_6BrArgsE")
+               + f"Lb{int(held)}ELi{heldi}E" + "EEvNS_6BrArgsE")
     assert mangled in usage, sorted(k for k in usage if "blind_rotate" in k)
     return mangled, usage[mangled]
 
@@ -75,6 +75,15 @@ def test_held_root_kernels_fit_two_waves_without_scratch(compiled, args):
     the whole job (the tuned ones at N = 1024 and for the one-limb key)."""
     usage, _ = compiled
     _, u = _br(usage, args, held=True)
+    assert u.get("ScratchSize", 0) == 0, u
+    assert u.get("Occupancy", 0) >= 2, u
+
+
+def test_held_inverse_root_kernel_fits_two_waves_without_scratch(compiled):
+    """The N = 1024 variant holding both the forward and the inverse
+    transforms' per-thread roots for the whole job."""
+    usage, _ = compiled
+    _, u = _br(usage, (10, 3, 7, 1, 0, 2, 1, 1), held=True, heldi=2)
     assert u.get("ScratchSize", 0) == 0, u
     assert u.get("Occupancy", 0) >= 2, u
 
