@@ -1235,8 +1235,10 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
 // N = 2048, two key limbs: (3, 2), (0, 1), (0, 2), (1, 1), (3, 2, 4),
 // (3, 2, 2), (0, 2, 2), (1, 1, 2), (0, 1, 2); N = 2048, one limb: (2, 2),
 // (1, 2), (0, 2), (0, 2, 2) with held forward roots, (1, 2, 4), (1, 2, 2),
-// and (3, 2), (0, 2), (1, 2) with held forward roots.  Split launches (two polynomial groups per job) use (1, 2) at
-// N = 1024, (0, 1) at N = 2048 with two limbs and (1, 2) with one.  The
+// and (3, 2), (0, 2), (1, 2) with held forward roots.  Split launches (two
+// polynomial groups per job) use (1, 2) with held forward roots at N = 1024,
+// (0, 1) at N = 2048 with two limbs and (1, 2) with one; the paired launch
+// (N = 1024) uses (1, 1) with the forward and inverse roots held.  The
 // one-limb N = 2048 key has no row form (two of its four groups would run
 // no inverse transform, so the groups' barrier sequences would differ).
 int blind_rotate_variants(uint32_t N) { return N == 1024 ? 11 : N == 2048 ? 9 : 0; }
@@ -1249,15 +1251,18 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
   const dim3 g((uint32_t)jobs);
   const bool split = groups == kBrTwo || (groups == kBrTwoPaired && N != 1024);
   if (groups == kBrTwoPaired && N == 1024) {
-    // two jobs of two groups per workgroup: every SIMD of a CU holds one wave
-    blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2, 2><<<dim3((uint32_t)((jobs + 1) / 2)), 256, 0, st>>>(a);
+    // two jobs of two groups per workgroup: every SIMD of a CU holds one
+    // wave, so the allocation may take a SIMD's whole register file and
+    // hold the forward and inverse transforms' roots for the job
+    blind_rotate_kernel<10, 3, 7, 1, 1, 1, 2, 2, true, 2>
+        <<<dim3((uint32_t)((jobs + 1) / 2)), 256, 0, st>>>(a);
   } else if (groups == kBrRows && !(N == 2048 && a.limbs == 1)) {
     if (N == 1024) blind_rotate_halfrow_kernel<3, 7><<<g, 12 * 64, 0, st>>>(a);
     else if (N == 2048) blind_rotate_rows_kernel<11, 2, 10, 2><<<g, 4 * 128, 0, st>>>(a);
     else return -1;
   } else if (N == 1024) {
     if (split) {
-      blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2><<<g, 128, 0, st>>>(a);
+      blind_rotate_kernel<10, 3, 7, 1, 1, 2, 2, 1, true><<<g, 128, 0, st>>>(a);
     } else {
       const dim3 g8((uint32_t)((jobs + 7) / 8)), g4((uint32_t)((jobs + 3) / 4));
       switch (variant) {
