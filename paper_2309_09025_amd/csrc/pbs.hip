@@ -1234,8 +1234,9 @@ int launch_bsk_to_ntt(uint32_t N, uint32_t n, uint32_t l, uint32_t limbs,
 // (0, 2) with the forward and the inverse transforms' roots held;
 // N = 2048, two key limbs: (3, 2), (0, 1), (0, 2), (1, 1), (3, 2, 4),
 // (3, 2, 2), (0, 2, 2), (1, 1, 2), (0, 1, 2); N = 2048, one limb: (2, 2),
-// (1, 2), (0, 2), (0, 2, 2) with held forward roots, (1, 2, 4), (1, 2, 2),
-// and (3, 2), (0, 2), (1, 2) with held forward roots.  Split launches (two
+// (1, 2), (0, 2), (0, 2, 2) with held forward and round-B' inverse roots,
+// (1, 2, 4), (1, 2, 2), (3, 2) and (0, 2) with held forward and round-B'
+// inverse roots, and (1, 2) with held forward roots.  Split launches (two
 // polynomial groups per job) use (1, 2) with held forward roots at N = 1024,
 // (0, 1) at N = 2048 with two limbs and (1, 2) with one; the paired launch
 // (N = 1024) uses (1, 1) with the forward and inverse roots held.  The
@@ -1290,11 +1291,11 @@ int launch_blind_rotate(uint32_t N, const BrArgs& args, size_t jobs, int variant
         case 0: blind_rotate_kernel<11, 2, 10, 1, 2, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 1: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1><<<g, 128, 0, st>>>(a); break;
         case 2: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1><<<g, 128, 0, st>>>(a); break;
-        case 3: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 2, true><<<g2, 256, 0, st>>>(a); break;
+        case 3: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 2, true, 1><<<g2, 256, 0, st>>>(a); break;
         case 4: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 4><<<g4, 512, 0, st>>>(a); break;
         case 5: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 2><<<g2, 256, 0, st>>>(a); break;
-        case 6: blind_rotate_kernel<11, 2, 10, 1, 3, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
-        case 7: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
+        case 6: blind_rotate_kernel<11, 2, 10, 1, 3, 2, 1, 1, true, 1><<<g, 128, 0, st>>>(a); break;
+        case 7: blind_rotate_kernel<11, 2, 10, 1, 0, 2, 1, 1, true, 1><<<g, 128, 0, st>>>(a); break;
         case 8: blind_rotate_kernel<11, 2, 10, 1, 1, 2, 1, 1, true><<<g, 128, 0, st>>>(a); break;
         default: return -2;
       }

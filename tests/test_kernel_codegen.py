@@ -65,15 +65,16 @@ def test_two_wave_kernels_have_no_scratch(compiled, args):
     assert u.get("Occupancy", 0) >= 2, u
 
 
-@pytest.mark.parametrize("args", [(10, 3, 7, 1, 0, 2, 1, 1), (10, 3, 7, 1, 3, 2, 1, 1),
-                                  (10, 3, 7, 1, 1, 2, 1, 1), (11, 2, 10, 1, 3, 2, 1, 1),
-                                  (11, 2, 10, 1, 0, 2, 1, 1), (11, 2, 10, 1, 1, 2, 1, 1),
-                                  (11, 2, 10, 1, 0, 2, 1, 2)])
-def test_held_root_kernels_fit_two_waves_without_scratch(compiled, args):
+@pytest.mark.parametrize("args,heldi", [((10, 3, 7, 1, 0, 2, 1, 1), 0), ((10, 3, 7, 1, 3, 2, 1, 1), 0),
+                                        ((10, 3, 7, 1, 1, 2, 1, 1), 0), ((11, 2, 10, 1, 3, 2, 1, 1), 1),
+                                        ((11, 2, 10, 1, 0, 2, 1, 1), 1), ((11, 2, 10, 1, 1, 2, 1, 1), 0),
+                                        ((11, 2, 10, 1, 0, 2, 1, 2), 1)])
+def test_held_root_kernels_fit_two_waves_without_scratch(compiled, args, heldi):
     """The variants holding the forward transforms' roots in registers for
-    the whole job (the tuned ones at N = 1024 and for the one-limb key)."""
+    the whole job (and, for the one-limb key, the inverse transforms' round-B'
+    roots)."""
     usage, _ = compiled
-    _, u = _br(usage, args, held=True)
+    _, u = _br(usage, args, held=True, heldi=heldi)
     assert u.get("ScratchSize", 0) == 0, u
     assert u.get("Occupancy", 0) >= 2, u
 
