@@ -80,11 +80,18 @@ KERNEL_SOURCES = ["paper_2309_09025_amd/csrc/pbs.hip", "paper_2309_09025_amd/csr
 
 
 def _sources_sha():
+    """Hash of the kernel sources without comments and blank space, so that
+    counter runs stay attached to the code they measured across edits of
+    comments only."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -579,8 +579,8 @@ blind_rotate_rows_kernel(BrArgs a) {
 // the roots of the full transform.  Likewise the inverse's stages 0 .. 8 act
 // within the halves of the bit-reversed order, and only its last stage
 // pairs i with i + N/2.  So a job runs as 2l x 2 = 12 waves, one per (digit
-// row, half), 8 values per thread, three per SIMD in the forward phase (the
-// one-wave-per-row kernel puts two rows on two of the four SIMDs), and the
+// row, half), 8 values per thread, three per SIMD in the forward phase (one
+// wave per row would put two rows on two of the four SIMDs), and the
 // 2 x 2 (output, half) inverse transforms run on four waves, one per SIMD.
 // The stages, roots, reduction points and products are those of the other
 // kernels, so the bits are the same.
@@ -615,8 +615,8 @@ __device__ __forceinline__ void reduce8(double x[8]) {
   for (int r = 0; r < 8; ++r) x[r] = redc(x[r]);
 }
 
-// One stage in a round: pairs registers r and r | 2^b, root w[r >> (b+1)]
-// (forward, decimation in frequency).
+// One forward stage in a round (the butterfly of fwd_stages_reg): pairs
+// registers r and r | 2^b, root w[r >> (b+1)].
 template <int B, int NW>
 __device__ __forceinline__ void hfwd_stage(double x[8], const double* w) {
 #pragma unroll
