@@ -288,8 +288,8 @@ FS_API void fs_devkey_free(fs_devkey* dk);
 /* WeightSum on ciphertexts (Sec. 4.1, Eq. "noise grows"):
  * y[o] = add[o] + sum_i W[o][i] * x[i], word by word mod 2^32.
  * W: dev int32 [O][I]; x: dev [I][dim]; add: dev [O][dim] or NULL;
- * y: dev [O][dim]; y == add is allowed (in-place accumulate), y must not
- * overlap x.  dim = ciphertext width: n+1 under s, or N+1 for the
+ * y: dev [O][dim]; y == add is allowed (in-place accumulate); otherwise y
+ * must not overlap add, and never x.  dim = ciphertext width: n+1 under s, or N+1 for the
  * ciphertexts under z that the key-switch-first order keeps between
  * bootstrappings (fs_pbs_lif_ks_first), hence an argument. */
 FS_API int fs_lwe_linear(fs_ctx* ctx, const int32_t* W, size_t O, size_t I, uint32_t dim,

@@ -45,6 +45,46 @@ lwe_linear_kernel(const int32_t* __restrict__ W, uint32_t O, uint32_t I, uint32_
   }
 }
 
+// Split form for layers too small to fill the device: blockIdx.z takes
+// inputs [z KC, (z + 1) KC) and adds its partial sums into y with 32-bit
+// atomics (sums mod 2^32 do not depend on the order); y already holds the
+// add rows or zeros (lwe_fill_kernel).
+template <int OT>
+__global__ void __launch_bounds__(256)
+lwe_linear_split_kernel(const int32_t* __restrict__ W, uint32_t O, uint32_t I, uint32_t KC,
+                        uint32_t dim, const uint32_t* __restrict__ x, uint32_t* y) {
+  const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t o0 = blockIdx.y * OT;
+  const uint32_t i0 = blockIdx.z * KC;
+  const uint32_t i1 = i0 + KC < I ? i0 + KC : I;
+  uint32_t acc[OT];
+#pragma unroll
+  for (int k = 0; k < OT; ++k) acc[k] = 0u;
+  const bool live = w < dim;
+  const uint32_t wc = live ? w : 0;
+  for (uint32_t i = i0; i < i1; ++i) {
+    const uint32_t xv = x[(size_t)i * dim + wc];
+#pragma unroll
+    for (int k = 0; k < OT; ++k) {
+      const uint32_t o = o0 + k < O ? o0 + k : O - 1;
+      acc[k] += (uint32_t)W[(size_t)o * I + i] * xv;
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < OT; ++k) {
+    const uint32_t o = o0 + k;
+    if (o < O) atomicAdd(&y[(size_t)o * dim + w], acc[k]);
+  }
+}
+
+// y = src (or zeros when src is null), `words` words.
+__global__ void __launch_bounds__(256)
+lwe_fill_kernel(const uint32_t* src, size_t words, uint32_t* y) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < words) y[i] = src ? src[i] : 0u;
+}
+
 // Convolution: block = 256 words of one output position (co, oy, ox).
 __global__ void __launch_bounds__(256)
 lwe_conv2d_kernel(const int32_t* __restrict__ W, uint32_t Ci, uint32_t H, uint32_t Wd,
@@ -95,12 +135,33 @@ lwe_add_plain_kernel(const uint32_t* x, const int32_t* c, uint32_t delta, size_t
     if (e_ != hipSuccess) return (int)e_; \
   } while (0)
 
+// A layer whose output tiles give fewer than kLinearBlocks workgroups has
+// its inputs split into up to 16 chunks, so that the device holds enough
+// waves to hide the load latency of its long reduction.
+constexpr uint32_t kLinearBlocks = 2048;
+
 int launch_lwe_linear(const int32_t* W, size_t O, size_t I, uint32_t dim, const uint32_t* x,
                       const uint32_t* add, uint32_t* y, hipStream_t st) {
   if (O == 0) return 0;
   constexpr int OT = 8;
-  dim3 g((dim + 255) / 256, (uint32_t)((O + OT - 1) / OT));
-  lwe_linear_kernel<OT><<<g, 256, 0, st>>>(W, (uint32_t)O, (uint32_t)I, dim, x, add, y);
+  const uint32_t bx = (dim + 255) / 256, by = (uint32_t)((O + OT - 1) / OT);
+  uint32_t split = kLinearBlocks / (bx * by);
+  if (split > 16) split = 16;
+  if (split > I / 64) split = (uint32_t)(I / 64);  // chunks of at least 64 inputs
+  if (split <= 1) {
+    lwe_linear_kernel<OT><<<dim3(bx, by), 256, 0, st>>>(W, (uint32_t)O, (uint32_t)I, dim, x, add, y);
+    FS_LAUNCH_CHECK();
+    return 0;
+  }
+  const uint32_t kc = (uint32_t)((I + split - 1) / split);
+  split = (uint32_t)((I + kc - 1) / kc);
+  if (add != y) {  // y = add (or 0); with y == add it already holds the rows
+    const size_t words = O * (size_t)dim;
+    lwe_fill_kernel<<<dim3((uint32_t)((words + 255) / 256)), 256, 0, st>>>(add, words, y);
+    FS_LAUNCH_CHECK();
+  }
+  lwe_linear_split_kernel<OT><<<dim3(bx, by, split), 256, 0, st>>>(W, (uint32_t)O, (uint32_t)I, kc,
+                                                                   dim, x, y);
   FS_LAUNCH_CHECK();
   return 0;
 }
