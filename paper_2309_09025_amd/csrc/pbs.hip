@@ -785,6 +785,7 @@ blind_rotate_halfrow_kernel(BrArgs a) {
   constexpr uint32_t HALF = 1u << (BG - 1);
   constexpr uint32_t NU = LOGN + 1;
   static_assert(NW >= 4, "four waves run the inverse transforms");
+  static_assert(2 * HALF <= 256, "the first two stages come from the digit tables");
   __shared__ double lds_all[NW][512 + 32];
   __shared__ double sums[2][2][8][TP];  // [output][half][r][t]
   __shared__ uint32_t acc[2][N];
