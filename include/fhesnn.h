@@ -213,8 +213,10 @@ FS_API int fs_ctx_admission(fs_ctx* ctx, size_t* budget, size_t* admitted);
 
 /* Tuning of the blind-rotation kernel.  Every variant computes the same
  * bits; they differ in when the key slice of a digit row is requested
- * (before or after its forward transform) and in the register budget the
- * compiler was held to (waves per SIMD).  fs_br_variants(N) returns the
+ * (before or after its forward transform), in the register budget the
+ * compiler was held to (waves per SIMD), in how many jobs share a workgroup
+ * in lockstep, and in which transform roots stay in registers for the whole
+ * job.  fs_br_variants(N) returns the
  * number of variants for ring degree N (0 if N is not supported);
  * fs_ctx_set_br_variant selects one for N on this context (default 0).
  * The autotuner times them and picks. */
