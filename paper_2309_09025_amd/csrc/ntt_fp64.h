@@ -182,8 +182,13 @@ __device__ __forceinline__ void wave_sync() {
 // exchange crosses waves and keeps the barrier between its writes and
 // reads, but not the one after the reads: the next access of another wave
 // to the slots read here comes after the next transform's entry barrier.
-template <int LOGN, int LO_FROM, int LO_TO, bool LEAN = false>
+// PAIR: the next stage's first butterflies pair registers r and r + PAIR;
+// the reads are requested in the order r, r + 1, r + PAIR, r + PAIR + 1, ...
+// (the compiler merges each two adjacent registers into one paired read), so
+// that the first butterflies wait for two paired reads instead of five.
+template <int LOGN, int LO_FROM, int LO_TO, bool LEAN = false, int PAIR = 8>
 __device__ __forceinline__ void exchange(double x[16], double* lds, int t) {
+  static_assert(PAIR >= 2 && PAIR <= 8 && (PAIR & (PAIR - 1)) == 0, "pairs of registers");
   constexpr int TP = (1 << LOGN) / 16;
   static_assert(!LEAN || TP <= 64 || (TP == 128 && LOGN == 11), "lean schedule derived for TP = 128");
   constexpr bool CROSS = LO_FROM == LOGN - 4 || LO_TO == LOGN - 4;  // into or out of round A
@@ -194,7 +199,13 @@ __device__ __forceinline__ void exchange(double x[16], double* lds, int t) {
   if constexpr (LEAN && !CROSS) wave_sync();
   else poly_sync<TP>();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = rp[slot_reg<LO_TO>(r)];
+  for (int g = 0; g < 16; g += 2) {
+    if (g & PAIR) continue;
+    x[g] = rp[slot_reg<LO_TO>(g)];
+    x[g + 1] = rp[slot_reg<LO_TO>(g + 1)];
+    x[g + PAIR] = rp[slot_reg<LO_TO>(g + PAIR)];
+    x[g + PAIR + 1] = rp[slot_reg<LO_TO>(g + PAIR + 1)];
+  }
   if constexpr (LEAN && TP > 64) wave_sync();
   else poly_sync<TP>();
 }
@@ -491,7 +502,8 @@ __device__ __forceinline__ void ntt_inv_reg(double x[16], double* lds, const Uni
   if constexpr (LEAN && S::TP > 64) {
     if (entry) __syncthreads();
   }
-  exchange<LOGN, 0, S::LOB, LEAN>(x, lds, t);
+  // round B' starts with stage 4, which pairs registers r and r + 2^(4 - LOB)
+  exchange<LOGN, 0, S::LOB, LEAN, (1 << (4 - S::LOB))>(x, lds, t);
   double wa_own[HELD == 2 ? 1 : R::IA];
   const double* wa = wa_own;
   if constexpr (HELD == 2) wa = held + R::IB;
